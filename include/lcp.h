@@ -1,0 +1,165 @@
+/*
+ * lcp.h - exact top-k retrieval under longest-common-prefix (LCP) similarity
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (section 2.1 of the paper, Definitions "LCP Similarity" and
+ * "Top-k LCP Retrieval"): a database of N categorical sequences of fixed
+ * length L over an alphabet of V symbols; for a query q of the same length,
+ * LCP(q, s) is the number of leading positions where q and s agree, and the
+ * answer is the k rows of highest LCP with ties broken by index.  This library
+ * breaks ties by the LOWER 0-based row id and lists every answer in rank order
+ * (LCP descending, id ascending), so results are bit-identical on every run
+ * (section 5.3, Theorem "Determinism").
+ *
+ * Index: instead of the paper's pointer trie (section 5.2, Algorithms 1-2) the
+ * rows are kept in lexicographic order (a trie's leaf order; tokens compared
+ * as unsigned integers, position 0 most significant, equal rows by ascending
+ * id) together with the adjacent-LCP array A[i] = LCP(T[i-1], T[i]), A[0] = 0.
+ * A trie node of depth d is a contiguous range of that order, the prefix
+ * bucket of section 6.2.  A query is answered by a batched search for its
+ * insertion point (the predecessor search of section 4.2), an outward walk
+ * over A that finds the cutoff LCP c at which the answer fills up, and a
+ * bounded scan of the rows tied at c for the lowest ids (the range-bounded
+ * scan of section 6.2 and Appendix D.1).  A plain full scan is provided as
+ * the brute-force path.
+ *
+ * Conventions for every entry point:
+ *   - Device pointers are HIP device allocations on the device that was
+ *     current when the index was built; host pointers are ordinary memory.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Query
+ *     calls only enqueue work; their outputs are valid once the stream has
+ *     been synchronised.  Calls on one stream run in order; calls on
+ *     different streams may overlap (each stream gets its own scratch).
+ *   - Tokens are uint8 when V <= 256 and uint16 (little-endian) otherwise;
+ *     token arrays are row-major [rows][L] with no padding between rows.
+ *   - Errors are returned as lcp_status codes and never abort; the message of
+ *     the calling thread's last failure is available from lcp_last_error().
+ */
+#ifndef LCP_H_
+#define LCP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lcp_index lcp_index; /* opaque; owns every device buffer of an index */
+
+typedef enum {
+    LCP_OK = 0,
+    LCP_EINVAL = -1,   /* an argument is out of its documented range */
+    LCP_ENOMEM = -2,   /* a device or pinned-host allocation failed */
+    LCP_EDEVICE = -3,  /* a HIP runtime call failed */
+    LCP_ERANGE = -4,   /* lcp_index_build found a token >= V */
+    LCP_ENOTIMPL = -5  /* the request is valid but not supported by this build */
+} lcp_status;
+
+#define LCP_L_MAX 255   /* LCP values are stored in one byte */
+#define LCP_K_MAX 1024  /* largest k accepted per query */
+
+/*
+ * Build an index over N rows (section 5.2, the sorted-order equivalent of
+ * Algorithms 1-2: leaf order of the trie with posting lists in id order).
+ *
+ *   tokens : device, [N][L] uint8 (V <= 256) or uint16 (V > 256).  The
+ *            index copies them; the caller may free `tokens` after return.
+ *   N      : 1 <= N < 2^31.      L : 1 <= L <= LCP_L_MAX.
+ *   V      : 1 <= V <= 65536; every token must be < V.
+ *   stream : stream the build runs on; the call synchronises it before it
+ *            returns, so the index is ready on return.
+ *   out    : receives the new handle (set to NULL on failure).
+ *
+ * Errors: LCP_EINVAL (bad sizes or NULL pointers), LCP_ERANGE (a token >= V;
+ * nothing is kept), LCP_ENOMEM, LCP_EDEVICE.
+ */
+lcp_status lcp_index_build(const void* tokens, int64_t N, int32_t L, int32_t V, void* stream,
+                           lcp_index** out);
+
+/*
+ * Index path: exact top-k for Q queries (section 2.1 definition; method of
+ * sections 4.2, 5.3 and 6.2 on the sorted order).
+ *
+ *   queries : device, [Q][L], same token width as the index.  Query tokens
+ *             are not checked against V: any value compares as an integer.
+ *   Q       : 0 <= Q < 2^31 (Q = 0 is a no-op).
+ *   k       : HOST array of Q values, 1 <= k[i] <= LCP_K_MAX.  Read during
+ *             the call only.
+ *   out_ids, out_lcp : device int32 arrays of sum(k) entries.  Query i owns
+ *             entries [off_i, off_i + k[i]) with off_i = k[0] + ... + k[i-1];
+ *             they hold its answer in rank order (LCP descending, id
+ *             ascending).  When k[i] > N the last k[i] - N entries are -1.
+ *
+ * Errors: LCP_EINVAL (NULL handle or pointers, Q < 0, k out of range),
+ * LCP_ENOMEM, LCP_EDEVICE.  Outputs are unspecified after an error.
+ */
+lcp_status lcp_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,
+                    int32_t* out_ids, int32_t* out_lcp, void* stream);
+
+/*
+ * Plain path: the same answer as lcp_topk computed by brute force (LCP of every
+ * query against all N rows, then per-query top-k; the "full scan" the paper
+ * compares against in section 7, Table "TAL range-scan vs full-scan").
+ * Arguments, output layout and errors are those of lcp_topk.
+ */
+lcp_status lcp_scan_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,
+                         int32_t* out_ids, int32_t* out_lcp, void* stream);
+
+/*
+ * Device-side variants for callers that keep k and the output offsets on the
+ * device (serving loops, captured graphs): no host staging, no host sync.
+ *
+ *   k_dev   : device int32 [Q], 1 <= k_dev[i] <= k_max (not re-checked on the
+ *             device: a value outside that range yields unspecified output
+ *             for that query, never a write outside [off_dev[i], off_dev[i+1])).
+ *   off_dev : device int64 [Q+1], off_dev[0] = 0, off_dev[i+1] = off_dev[i] + k_dev[i].
+ *   k_max   : host upper bound on every k_dev[i]; 1 <= k_max <= LCP_K_MAX.
+ * Other arguments as lcp_topk.
+ */
+lcp_status lcp_topk_dev(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k_dev,
+                        const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
+                        void* stream);
+lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_t Q,
+                             const int32_t* k_dev, const int64_t* off_dev, int32_t k_max,
+                             int32_t* out_ids, int32_t* out_lcp, void* stream);
+
+/* Synchronise every stream the index has been used on, then free it.  NULL is a no-op. */
+void lcp_index_free(lcp_index* index);
+
+/* Message of the calling thread's most recent failed call ("" if none).  The
+ * pointer stays valid until the thread's next failing call. */
+const char* lcp_last_error(void);
+
+/*
+ * Introspection (tests, tooling).  Any output pointer may be NULL.
+ *   token_bytes : 1 or 2.   row_words : 32-bit words per stored row.
+ */
+lcp_status lcp_index_info(const lcp_index* index, int64_t* N, int32_t* L, int32_t* V,
+                          int32_t* token_bytes, int32_t* row_words);
+
+/*
+ * Read-only device views owned by the index (valid until lcp_index_free):
+ *   perm        : int32 [N], perm[i] = id of the i-th row in sorted order.
+ *   adj_lcp     : uint8 [N], A[i] = LCP(T[i-1], T[i]), A[0] = 0.
+ *   sorted_keys : uint32 [N][row_words], sorted rows in key form (tokens
+ *                 packed big-end first into 32-bit words, zero padded).
+ *   id_keys     : uint32 [N][row_words], the same rows in id order.
+ */
+lcp_status lcp_index_views(const lcp_index* index, const int32_t** perm, const uint8_t** adj_lcp,
+                           const uint32_t** sorted_keys, const uint32_t** id_keys);
+
+/*
+ * Kernel timing for benchmarks: when enabled, each query call records HIP
+ * events on its stream around its main kernel (the fused index-path kernel or
+ * the scan kernel).  lcp_kernel_time synchronises those events and returns
+ * the summed milliseconds and launch count since the last reset.
+ *   which : 0 = index-path kernel, 1 = scan kernel, 2 = scan merge kernel.
+ */
+lcp_status lcp_set_kernel_timing(const lcp_index* index, int32_t enable);
+lcp_status lcp_kernel_time(const lcp_index* index, int32_t which, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCP_H_ */

@@ -1,0 +1,502 @@
+// C-ABI of the library (declared in include/lcp.h): argument checks, device
+// buffers, per-stream scratch and the orchestration of the build and query
+// kernels.  Every step of the computation runs in the HIP kernels; this file
+// only moves sizes, pointers and the host-side k[] array.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lcp.h"
+#include "launch.hpp"
+
+using namespace lcpx;
+
+namespace {
+
+thread_local std::string g_err;
+
+lcp_status fail(lcp_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+lcp_status fail(lcp_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                 \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? LCP_ENOMEM : LCP_EDEVICE, "%s: %s (%s:%d)", #expr, \
+                        hipGetErrorString(e_), __FILE__, __LINE__);                                   \
+    } while (0)
+
+// Pinned staging slot for a host k[] array; reused once its copy has run.
+struct Slot {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+struct StreamCtx {
+    hipStream_t stream = nullptr;
+    Slot slots[4];
+    int next = 0;
+    int32_t* d_k = nullptr;
+    int64_t* d_off = nullptr;
+    size_t cap_q = 0;
+    uint64_t* d_part = nullptr;
+    size_t cap_part = 0;
+};
+
+struct TimedLaunch {
+    int which;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct lcp_index {
+    int device = 0;
+    int64_t N = 0;
+    int32_t L = 0, V = 0;
+    RowGeo g{};
+    uint32_t* d_rows = nullptr;    // id order, key form
+    uint32_t* d_sorted = nullptr;  // sorted order, key form
+    int32_t* d_perm = nullptr;
+    uint8_t* d_A = nullptr;
+
+    mutable std::mutex mu;
+    mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
+    mutable bool timing = false;
+    mutable std::vector<TimedLaunch> timed;
+    mutable std::vector<hipEvent_t> event_pool;
+    mutable double acc_ms[3] = {0, 0, 0};
+    mutable int64_t acc_n[3] = {0, 0, 0};
+
+    IndexView view() const {
+        IndexView v;
+        v.sorted = d_sorted;
+        v.rows = d_rows;
+        v.perm = d_perm;
+        v.A = d_A;
+        v.N = N;
+        v.g = g;
+        return v;
+    }
+};
+
+namespace {
+
+void free_ctx(StreamCtx* c) {
+    for (auto& s : c->slots) {
+        if (s.done) hipEventDestroy(s.done);
+        if (s.host) hipHostFree(s.host);
+    }
+    if (c->d_k) hipFree(c->d_k);
+    if (c->d_off) hipFree(c->d_off);
+    if (c->d_part) hipFree(c->d_part);
+    delete c;
+}
+
+// caller holds idx->mu
+lcp_status get_ctx(const lcp_index* idx, hipStream_t s, StreamCtx** out) {
+    auto it = idx->ctx.find(s);
+    if (it != idx->ctx.end()) {
+        *out = it->second;
+        return LCP_OK;
+    }
+    StreamCtx* c = new StreamCtx();
+    c->stream = s;
+    for (auto& sl : c->slots) {
+        hipError_t e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            free_ctx(c);
+            return fail(LCP_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        }
+    }
+    idx->ctx[s] = c;
+    *out = c;
+    return LCP_OK;
+}
+
+lcp_status ensure_q(StreamCtx* c, size_t Q) {
+    if (Q <= c->cap_q) return LCP_OK;
+    size_t cap = std::max<size_t>(Q, 2 * c->cap_q);
+    HIP_TRY(hipStreamSynchronize(c->stream));  // earlier calls may still read the old buffers
+    if (c->d_k) hipFree(c->d_k);
+    if (c->d_off) hipFree(c->d_off);
+    c->d_k = nullptr;
+    c->d_off = nullptr;
+    c->cap_q = 0;
+    HIP_TRY(hipMalloc(&c->d_k, cap * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&c->d_off, (cap + 1) * sizeof(int64_t)));
+    c->cap_q = cap;
+    return LCP_OK;
+}
+
+lcp_status ensure_part(StreamCtx* c, size_t entries) {
+    if (entries <= c->cap_part) return LCP_OK;
+    size_t cap = std::max(entries, c->cap_part + c->cap_part / 2);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->d_part) hipFree(c->d_part);
+    c->d_part = nullptr;
+    c->cap_part = 0;
+    HIP_TRY(hipMalloc(&c->d_part, cap * sizeof(uint64_t)));
+    c->cap_part = cap;
+    return LCP_OK;
+}
+
+hipEvent_t take_event(const lcp_index* idx) {
+    if (!idx->event_pool.empty()) {
+        hipEvent_t e = idx->event_pool.back();
+        idx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Copy host k[] and its exclusive prefix sum to the stream's device buffers.
+lcp_status stage_k(const lcp_index* idx, StreamCtx* c, int64_t Q, const int32_t* k, int32_t* k_max_out) {
+    int32_t kmax = 1;
+    for (int64_t i = 0; i < Q; ++i) {
+        if (k[i] < 1 || k[i] > LCP_K_MAX)
+            return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
+        kmax = std::max(kmax, k[i]);
+    }
+    lcp_status st = ensure_q(c, (size_t)Q);
+    if (st != LCP_OK) return st;
+    const size_t bytes = (size_t)Q * sizeof(int32_t) + (size_t)(Q + 1) * sizeof(int64_t);
+    Slot& sl = c->slots[c->next];
+    c->next = (c->next + 1) % 4;
+    if (sl.pending) {
+        HIP_TRY(hipEventSynchronize(sl.done));
+        sl.pending = false;
+    }
+    if (sl.cap < bytes) {
+        if (sl.host) hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.cap = 0;
+        HIP_TRY(hipHostMalloc(&sl.host, bytes, hipHostMallocDefault));
+        sl.cap = bytes;
+    }
+    int64_t* off = reinterpret_cast<int64_t*>(sl.host);
+    int32_t* kk = reinterpret_cast<int32_t*>(off + Q + 1);
+    off[0] = 0;
+    for (int64_t i = 0; i < Q; ++i) off[i + 1] = off[i] + k[i];
+    std::memcpy(kk, k, (size_t)Q * sizeof(int32_t));
+    HIP_TRY(hipMemcpyAsync(c->d_off, off, (size_t)(Q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_k, kk, (size_t)Q * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipEventRecord(sl.done, c->stream));
+    sl.pending = true;
+    *k_max_out = kmax;
+    (void)idx;
+    return LCP_OK;
+}
+
+lcp_status check_query_args(const lcp_index* idx, const void* queries, int64_t Q, const void* out_ids,
+                            const void* out_lcp) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (Q < 0 || Q > INT32_MAX) return fail(LCP_EINVAL, "Q = %lld is outside [0, 2^31)", (long long)Q);
+    if (Q > 0 && (!queries || !out_ids || !out_lcp)) return fail(LCP_EINVAL, "NULL queries or output pointer");
+    return LCP_OK;
+}
+
+enum class Path { Index, Scan };
+
+// Queries per launch: the index kernel's grid is Q/4 blocks; the scan's grid y
+// is Q/(4*tq) <= 65535 query groups.
+constexpr int64_t kSliceIndex = 1 << 20;
+constexpr int64_t kSliceScan = 65535 * 4;
+
+lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
+                   const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp, hipStream_t s,
+                   StreamCtx* c) {
+    HIP_TRY(hipSetDevice(idx->device));
+    const IndexView ix = idx->view();
+    const size_t row_bytes = (size_t)idx->L * idx->g.tb;
+    const int64_t slice = path == Path::Index ? kSliceIndex : kSliceScan;
+    for (int64_t q0 = 0; q0 < Q; q0 += slice) {
+        QueryBatch qb;
+        qb.raw = static_cast<const uint8_t*>(queries) + (size_t)q0 * row_bytes;
+        qb.Q = std::min(slice, Q - q0);
+        qb.k = k_dev + q0;
+        qb.off = off_dev + q0;
+        qb.k_max = k_max;
+        qb.out_ids = out_ids;  // offsets are absolute
+        qb.out_lcp = out_lcp;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (idx->timing) {
+            int need = path == Path::Index ? 2 : 3;
+            for (int i = 0; i < need; ++i) ev[i] = take_event(idx);
+        }
+        if (path == Path::Index) {
+            if (ev[0]) HIP_TRY(hipEventRecord(ev[0], s));
+            HIP_TRY(launch_index_query(ix, qb, s));
+            if (ev[1]) {
+                HIP_TRY(hipEventRecord(ev[1], s));
+                idx->timed.push_back({0, ev[0], ev[1]});
+            }
+        } else {
+            const ScanPlan plan = plan_scan(idx->N, qb.Q, k_max);
+            lcp_status st = ensure_part(c, scan_partial_entries(plan, qb.Q, k_max));
+            if (st != LCP_OK) return st;
+            HIP_TRY(launch_scan(ix, qb, plan, c->d_part, s, ev[0], ev[1], ev[2]));
+            if (ev[0] && ev[1] && ev[2]) {
+                // the merge interval starts where the scan interval ends
+                idx->timed.push_back({1, ev[0], ev[1]});
+                idx->timed.push_back({2, ev[1], ev[2]});
+            }
+        }
+    }
+    return LCP_OK;
+}
+
+lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k,
+                      int32_t* out_ids, int32_t* out_lcp, void* stream) {
+    lcp_status st = check_query_args(idx, queries, Q, out_ids, out_lcp);
+    if (st != LCP_OK) return st;
+    if (Q == 0) return LCP_OK;
+    if (!k) return fail(LCP_EINVAL, "k is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(idx->mu);
+    HIP_TRY(hipSetDevice(idx->device));
+    StreamCtx* c = nullptr;
+    st = get_ctx(idx, s, &c);
+    if (st != LCP_OK) return st;
+    int32_t kmax = 1;
+    st = stage_k(idx, c, Q, k, &kmax);
+    if (st != LCP_OK) return st;
+    return run_dev(idx, path, queries, Q, c->d_k, c->d_off, kmax, out_ids, out_lcp, s, c);
+}
+
+lcp_status query_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
+                     const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp, void* stream) {
+    lcp_status st = check_query_args(idx, queries, Q, out_ids, out_lcp);
+    if (st != LCP_OK) return st;
+    if (Q == 0) return LCP_OK;
+    if (!k_dev || !off_dev) return fail(LCP_EINVAL, "NULL k_dev or off_dev");
+    if (k_max < 1 || k_max > LCP_K_MAX) return fail(LCP_EINVAL, "k_max = %d is outside [1, %d]", k_max, LCP_K_MAX);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(idx->mu);
+    StreamCtx* c = nullptr;
+    st = get_ctx(idx, s, &c);
+    if (st != LCP_OK) return st;
+    return run_dev(idx, path, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, s, c);
+}
+
+struct BuildTemps {
+    uint32_t* dense = nullptr;
+    uint32_t* keys[2] = {nullptr, nullptr};
+    int32_t* vals[2] = {nullptr, nullptr};
+    uint32_t* counts = nullptr;
+    uint32_t* flags = nullptr;  // [0] = bad token, [1..Wd] = varying bits
+    ~BuildTemps() {
+        if (dense) hipFree(dense);
+        for (int i = 0; i < 2; ++i) {
+            if (keys[i]) hipFree(keys[i]);
+            if (vals[i]) hipFree(vals[i]);
+        }
+        if (counts) hipFree(counts);
+        if (flags) hipFree(flags);
+    }
+};
+
+void destroy_index(lcp_index* idx) {
+    if (!idx) return;
+    for (auto& kv : idx->ctx) {
+        hipStreamSynchronize(kv.first);
+        free_ctx(kv.second);
+    }
+    idx->ctx.clear();
+    for (auto& t : idx->timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    for (auto e : idx->event_pool) hipEventDestroy(e);
+    if (idx->d_rows) hipFree(idx->d_rows);
+    if (idx->d_sorted) hipFree(idx->d_sorted);
+    if (idx->d_perm) hipFree(idx->d_perm);
+    if (idx->d_A) hipFree(idx->d_A);
+    delete idx;
+}
+
+lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
+    const int64_t N = idx->N;
+    const RowGeo g = idx->g;
+    const int W = g.W;
+    int dbits = 1;
+    while ((1 << dbits) < idx->V && dbits < 16) ++dbits;
+    const int Wd = (idx->L * dbits + 31) / 32;
+    BuildTemps t;
+    HIP_TRY(hipMalloc(&idx->d_rows, (size_t)N * W * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&idx->d_sorted, (size_t)N * W * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&idx->d_perm, (size_t)N * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&idx->d_A, (size_t)N));
+    HIP_TRY(hipMalloc(&t.dense, (size_t)N * Wd * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&t.flags, (size_t)(1 + Wd) * sizeof(uint32_t)));
+    HIP_TRY(hipMemsetAsync(t.flags, 0, (size_t)(1 + Wd) * sizeof(uint32_t), s));
+    HIP_TRY(launch_pack(tokens, N, g, (uint32_t)idx->V, dbits, Wd, idx->d_rows, t.dense, t.flags, s));
+    HIP_TRY(launch_varying_bits(t.dense, N, Wd, t.flags + 1, s));
+    std::vector<uint32_t> flags(1 + Wd);
+    HIP_TRY(hipMemcpyAsync(flags.data(), t.flags, flags.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flags[0]) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);
+
+    // stable LSD radix sort of ids by the dense key: last word first, low digit first
+    const int nt = radix_tiles(N);
+    HIP_TRY(hipMalloc(&t.counts, (size_t)nt * 256 * sizeof(uint32_t)));
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMalloc(&t.keys[b], (size_t)N * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&t.vals[b], (size_t)N * sizeof(int32_t)));
+    }
+    int cur = 0;
+    HIP_TRY(launch_iota(t.vals[cur], N, s));
+    for (int d = Wd - 1; d >= 0; --d) {
+        const uint32_t vary = flags[1 + d];
+        if (!vary) continue;
+        HIP_TRY(launch_gather_word(t.dense, t.vals[cur], N, Wd, d, t.keys[cur], s));
+        int last_digit = -1;
+        for (int dg = 0; dg < 4; ++dg)
+            if ((vary >> (8 * dg)) & 0xFFu) last_digit = dg;
+        for (int dg = 0; dg < 4; ++dg) {
+            if (!((vary >> (8 * dg)) & 0xFFu)) continue;
+            HIP_TRY(launch_radix_pass(t.keys[cur], t.vals[cur], N, 8 * dg, t.counts, t.keys[cur ^ 1],
+                                      t.vals[cur ^ 1], dg != last_digit, s));
+            cur ^= 1;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(idx->d_perm, t.vals[cur], (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_gather_rows(idx->d_rows, idx->d_perm, N, W, idx->d_sorted, s));
+    HIP_TRY(launch_adjacent_lcp(idx->d_sorted, N, g, idx->d_A, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lcp_status lcp_index_build(const void* tokens, int64_t N, int32_t L, int32_t V, void* stream, lcp_index** out) {
+    if (!out) return fail(LCP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!tokens) return fail(LCP_EINVAL, "tokens is NULL");
+    if (N < 1 || N > INT32_MAX) return fail(LCP_EINVAL, "N = %lld is outside [1, 2^31)", (long long)N);
+    if (L < 1 || L > LCP_L_MAX) return fail(LCP_EINVAL, "L = %d is outside [1, %d]", L, LCP_L_MAX);
+    if (V < 1 || V > 65536) return fail(LCP_EINVAL, "V = %d is outside [1, 65536]", V);
+    lcp_index* idx = new lcp_index();
+    hipError_t e = hipGetDevice(&idx->device);
+    if (e != hipSuccess) {
+        delete idx;
+        return fail(LCP_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    idx->N = N;
+    idx->L = L;
+    idx->V = V;
+    idx->g = make_geo(L, V <= 256 ? 1 : 2);
+    lcp_status st = build_into(idx, tokens, static_cast<hipStream_t>(stream));
+    if (st != LCP_OK) {
+        std::string msg = g_err;
+        hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        destroy_index(idx);
+        g_err = msg;
+        return st;
+    }
+    *out = idx;
+    return LCP_OK;
+}
+
+lcp_status lcp_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k, int32_t* out_ids,
+                    int32_t* out_lcp, void* stream) {
+    return query_host(index, Path::Index, queries, Q, k, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_scan_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,
+                         int32_t* out_ids, int32_t* out_lcp, void* stream) {
+    return query_host(index, Path::Scan, queries, Q, k, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_topk_dev(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k_dev,
+                        const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp, void* stream) {
+    return query_dev(index, Path::Index, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k_dev,
+                             const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
+                             void* stream) {
+    return query_dev(index, Path::Scan, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, stream);
+}
+
+void lcp_index_free(lcp_index* index) { destroy_index(index); }
+
+const char* lcp_last_error(void) { return g_err.c_str(); }
+
+lcp_status lcp_index_info(const lcp_index* idx, int64_t* N, int32_t* L, int32_t* V, int32_t* token_bytes,
+                          int32_t* row_words) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (N) *N = idx->N;
+    if (L) *L = idx->L;
+    if (V) *V = idx->V;
+    if (token_bytes) *token_bytes = idx->g.tb;
+    if (row_words) *row_words = idx->g.W;
+    return LCP_OK;
+}
+
+lcp_status lcp_index_views(const lcp_index* idx, const int32_t** perm, const uint8_t** adj_lcp,
+                           const uint32_t** sorted_keys, const uint32_t** id_keys) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (perm) *perm = idx->d_perm;
+    if (adj_lcp) *adj_lcp = idx->d_A;
+    if (sorted_keys) *sorted_keys = idx->d_sorted;
+    if (id_keys) *id_keys = idx->d_rows;
+    return LCP_OK;
+}
+
+lcp_status lcp_set_kernel_timing(const lcp_index* idx, int32_t enable) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    idx->timing = enable != 0;
+    return LCP_OK;
+}
+
+lcp_status lcp_kernel_time(const lcp_index* idx, int32_t which, double* total_ms, int64_t* launches) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (which < 0 || which > 2) return fail(LCP_EINVAL, "which = %d is outside [0, 2]", which);
+    std::lock_guard<std::mutex> lk(idx->mu);
+    // fold every recorded interval into the accumulators; events are recycled
+    std::vector<hipEvent_t> freed;
+    for (auto& t : idx->timed) {
+        HIP_TRY(hipEventSynchronize(t.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+        idx->acc_ms[t.which] += ms;
+        idx->acc_n[t.which] += 1;
+        freed.push_back(t.a);
+        freed.push_back(t.b);
+    }
+    idx->timed.clear();
+    std::sort(freed.begin(), freed.end());
+    freed.erase(std::unique(freed.begin(), freed.end()), freed.end());
+    for (auto e : freed) idx->event_pool.push_back(e);
+    if (total_ms) *total_ms = idx->acc_ms[which];
+    if (launches) *launches = idx->acc_n[which];
+    // reading resets the accumulator that was read
+    idx->acc_ms[which] = 0;
+    idx->acc_n[which] = 0;
+    return LCP_OK;
+}
+
+}  // extern "C"

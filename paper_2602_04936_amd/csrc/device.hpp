@@ -1,0 +1,237 @@
+// Device helpers shared by the index-build, index-query and scan kernels.
+//
+// Wave64 primitives for CDNA4 (gfx950), the "key form" of a row, and a
+// lane-distributed sorted list of 64-bit keys used for every exact top-k
+// selection in the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lcpx {
+
+constexpr int kWave = 64;
+constexpr uint64_t kKeyMax = ~0ull;
+
+// ---------------------------------------------------------------- wave ops
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// index of the lowest set bit of a non-zero mask
+__device__ __forceinline__ int low_lane(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+
+// number of set bits of m in lanes below the calling lane
+__device__ __forceinline__ int count_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    uint32_t lo = readlane((uint32_t)v, l);
+    uint32_t hi = readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
+    return (int64_t)readlane64((uint64_t)v, l);
+}
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// value of lane (lane - 1); lane 0 receives its own value
+__device__ __forceinline__ uint32_t from_lower_lane(uint32_t v) {
+    int src = lane_id() - 1;
+    src = src < 0 ? 0 : src;
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ __forceinline__ uint64_t from_lower_lane64(uint64_t v) {
+    return ((uint64_t)from_lower_lane((uint32_t)(v >> 32)) << 32) | from_lower_lane((uint32_t)v);
+}
+__device__ __forceinline__ int from_lane(int v, int src) {
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+// inclusive prefix minimum over the wave's lanes
+__device__ __forceinline__ int wave_prefix_min(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        int src = lane - d;
+        int o = from_lane(v, src < 0 ? 0 : src);
+        if (src >= 0) v = o < v ? o : v;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- rows
+//
+// Key form: a row of L tokens of `tb` bytes is stored as W = ceil(L*tb/4)
+// 32-bit words, tokens packed big-end first (token j of word w sits in bits
+// [32 - 8*tb*(j+1), 32 - 8*tb*j)), the tail of the last word zero.  Then
+//   - lexicographic order of rows == unsigned order of the word sequences,
+//   - the first differing word w and x = a[w] ^ b[w] give
+//     LCP = w * tokens_per_word + clz(x) / token_bits.
+
+struct RowGeo {
+    int L;          // tokens per row
+    int W;          // words per row
+    int tb;         // bytes per token (1 or 2)
+    int tpw_log2;   // log2(tokens per word): 2 for 1-byte tokens, 1 for 2-byte
+    int bits_log2;  // log2(bits per token): 3 or 4
+};
+
+__host__ __device__ inline RowGeo make_geo(int L, int tb) {
+    RowGeo g;
+    g.L = L;
+    g.tb = tb;
+    g.W = (L * tb + 3) / 4;
+    g.tpw_log2 = tb == 1 ? 2 : 1;
+    g.bits_log2 = tb == 1 ? 3 : 4;
+    return g;
+}
+
+__device__ __forceinline__ uint32_t raw_token(const void* base, int64_t idx, int tb) {
+    return tb == 1 ? (uint32_t)((const uint8_t*)base)[idx] : (uint32_t)((const uint16_t*)base)[idx];
+}
+
+// Key word w of the row starting at token index `row0` of a raw token array.
+__device__ __forceinline__ uint32_t key_word(const void* raw, int64_t row0, const RowGeo& g, int w) {
+    const int tpw = 1 << g.tpw_log2;
+    const int bits = 8 * g.tb;
+    uint32_t x = 0;
+    for (int t = 0; t < tpw; ++t) {
+        int j = w * tpw + t;
+        uint32_t v = j < g.L ? raw_token(raw, row0 + j, g.tb) : 0u;
+        x |= v << (32 - bits * (t + 1));
+    }
+    return x;
+}
+
+__device__ __forceinline__ int lcp_from_diff(int word, uint32_t x, const RowGeo& g) {
+    return (word << g.tpw_log2) + (__clz((int)x) >> g.bits_log2);
+}
+
+// Per-lane LCP and order of a stored row against a query held in LDS.
+// Lanes with act == false return lcp = -1, less = false.  The loop leaves as
+// soon as every active lane has found its first differing word.
+template <int VEC>
+__device__ __forceinline__ void compare_row(const uint32_t* __restrict__ row, const uint32_t* q, const RowGeo& g,
+                                            bool act, int& lcp, bool& less) {
+    int fw = -1;
+    uint32_t fx = 0;
+    bool lt = false;
+    bool open = act;
+    for (int w = 0; w < g.W; w += VEC) {
+        if (open) {
+            uint32_t r[VEC];
+            if constexpr (VEC == 4) {
+                uint4 v = *reinterpret_cast<const uint4*>(row + w);
+                r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+            } else if constexpr (VEC == 2) {
+                uint2 v = *reinterpret_cast<const uint2*>(row + w);
+                r[0] = v.x; r[1] = v.y;
+            } else {
+                r[0] = row[w];
+            }
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                uint32_t qq = q[w + j];
+                if (open && r[j] != qq) {
+                    fw = w + j;
+                    fx = r[j] ^ qq;
+                    lt = r[j] < qq;
+                    open = false;
+                }
+            }
+        }
+        if (ballot(open) == 0) break;
+    }
+    lcp = act ? (fw < 0 ? g.L : lcp_from_diff(fw, fx, g)) : -1;
+    less = act && fw >= 0 && lt;
+}
+
+// Same, starting after a known-equal first word (used by the scan's slow path).
+__device__ __forceinline__ int lcp_tail(const uint32_t* __restrict__ row, const uint32_t* q, const RowGeo& g,
+                                        int from_word) {
+    for (int w = from_word; w < g.W; ++w) {
+        uint32_t x = row[w] ^ q[w];
+        if (x) return lcp_from_diff(w, x, g);
+    }
+    return g.L;
+}
+
+// ---------------------------------------------------------------- keys
+//
+// Rank key of a (row id, LCP) pair: smaller key = better rank.
+__device__ __forceinline__ uint64_t rank_key(int lcp, uint32_t id) {
+    return ((uint64_t)(uint32_t)(255 - lcp) << 32) | id;
+}
+__device__ __forceinline__ int key_lcp(uint64_t k) { return 255 - (int)(k >> 32); }
+__device__ __forceinline__ int key_id(uint64_t k) { return (int)(uint32_t)k; }
+
+// ---------------------------------------------------------------- sorted list
+//
+// Ascending list of up to 64*NR keys spread over the wave: entry e lives in
+// register e / 64 of lane e % 64.  Unused entries hold kKeyMax.
+template <int NR>
+struct WaveList {
+    uint64_t v[NR];
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = kKeyMax;
+    }
+
+    // entry e (wave-uniform e)
+    __device__ __forceinline__ uint64_t get(int e) const {
+        uint64_t out = kKeyMax;
+        const int rr = e >> 6;
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (r == rr) out = readlane64(v[r], e & 63);
+        return out;
+    }
+
+    // insert one wave-uniform key at its rank; the last entry falls off
+    __device__ __forceinline__ void insert(uint64_t key) {
+        const int lane = lane_id();
+        int pos = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pos += popc64(ballot(v[r] < key));
+#pragma unroll
+        for (int r = NR - 1; r >= 0; --r) {
+            uint64_t prev = from_lower_lane64(v[r]);
+            if (r > 0) {
+                uint64_t carry = readlane64(v[r - 1], 63);
+                if (lane == 0) prev = carry;
+            }
+            const int e = r * 64 + lane;
+            v[r] = e > pos ? prev : (e == pos ? key : v[r]);
+        }
+    }
+
+    // Offer every lane's key where `pass` holds; afterwards entries [0, m)
+    // are the m smallest keys among the previous entries and the offers.
+    __device__ __forceinline__ void offer(uint64_t key, bool pass, int m) {
+        const int lane = lane_id();
+        uint64_t thr = get(m - 1);
+        pass = pass && key < thr;
+        uint64_t bal = ballot(pass);
+        while (bal) {
+            const int src = low_lane(bal);
+            insert(readlane64(key, src));
+            thr = get(m - 1);
+            pass = pass && lane != src && key < thr;
+            bal = ballot(pass);
+        }
+    }
+};
+
+}  // namespace lcpx
