@@ -1,0 +1,292 @@
+"""Continuous-batching serving loop over a resident index.
+
+Requests (a block of 1..B queries sharing one k) arrive over time.  The index
+stays resident in HBM; a fixed set of launch slots, one HIP stream each,
+carries work to the GPU.  Whenever a slot is free, the scheduler packs the
+oldest waiting requests that fit the slot's memory (query rows, k/offsets,
+output entries) into one call of the index path, so requests that arrive
+while others are on the GPU join the next launch and their work overlaps on
+the device with launches already in flight.  Each query's answer does not
+depend on which other queries share its launch (queries are independent and
+the kernels are deterministic), so a request's result is the same alone and in
+the mix.
+
+The paper's sustained benchmark issues one top-1 query at a time (section 7,
+Table "Sustained benchmark"; Appendix C); this loop is the batched, open-loop
+form of that measurement: latency = completion time - arrival time, reported
+as p50/p99 next to the achieved queries/s.
+
+`Scheduler` is pure host logic and is tested on the CPU with a fake executor;
+`GpuExecutor` is the only part that touches the device.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Deque, List, Optional
+
+import numpy as np
+
+__all__ = ["Request", "Scheduler", "GpuExecutor", "run_loop", "latency_report", "slot_capacities",
+           "requests_from_schedule", "run_served", "run_synchronous"]
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds since the start of the run
+    queries: np.ndarray     # [b, L] tokens
+    k: int
+    done: float = -1.0      # completion time (seconds since start)
+    ids: Optional[np.ndarray] = None   # [b, k]
+    lcps: Optional[np.ndarray] = None  # [b, k]
+
+    @property
+    def b(self) -> int:
+        return int(self.queries.shape[0])
+
+
+class Scheduler:
+    """FIFO admission into launch slots bounded by per-slot capacities.
+
+    cap_queries : query rows per launch
+    cap_entries : output entries (sum of k over the launch's queries) per launch
+    A request larger than a whole slot is rejected at submit time.
+    """
+
+    def __init__(self, cap_queries: int, cap_entries: int):
+        if cap_queries < 1 or cap_entries < 1:
+            raise ValueError("capacities must be positive")
+        self.cap_queries = cap_queries
+        self.cap_entries = cap_entries
+        self.pending: Deque[Request] = collections.deque()
+
+    def submit(self, req: Request):
+        if req.b > self.cap_queries or req.b * req.k > self.cap_entries:
+            raise ValueError(f"request {req.rid} ({req.b} queries, k={req.k}) exceeds one launch slot")
+        self.pending.append(req)
+
+    def next_batch(self) -> List[Request]:
+        """Oldest pending requests that fit one slot (possibly empty)."""
+        batch: List[Request] = []
+        nq = ne = 0
+        while self.pending:
+            r = self.pending[0]
+            if nq + r.b > self.cap_queries or ne + r.b * r.k > self.cap_entries:
+                break
+            batch.append(self.pending.popleft())
+            nq += r.b
+            ne += r.b * r.k
+        return batch
+
+    def __len__(self):
+        return len(self.pending)
+
+
+def slot_capacities(budget_bytes: int, n_slots: int, row_bytes: int, k_max: int = 100):
+    """Split a device-memory budget over the slots: each query row costs its
+    tokens + k and offset words, each output entry 8 bytes (id + LCP)."""
+    per_slot = budget_bytes // n_slots
+    per_query = row_bytes + 4 + 8 + 8 * k_max
+    cap_q = max(1, per_slot // per_query)
+    return int(cap_q), int(cap_q * k_max)
+
+
+class GpuExecutor:
+    """Launch slots on separate HIP streams; outputs come back to pinned host memory."""
+
+    def __init__(self, index, n_slots: int, cap_queries: int, cap_entries: int, scan: bool = False):
+        import torch
+        self.torch = torch
+        self.index = index
+        self.scan = scan
+        dev = index.device
+        L, tb = index.L, index.token_bytes
+        qdt = torch.uint8 if tb == 1 else torch.int16
+        self.slots = []
+        for _ in range(n_slots):
+            s = {
+                "stream": torch.cuda.Stream(device=dev),
+                "q_host": torch.empty((cap_queries, L), dtype=qdt, pin_memory=True),
+                "k_host": torch.empty(cap_queries, dtype=torch.int32, pin_memory=True),
+                "off_host": torch.empty(cap_queries + 1, dtype=torch.int64, pin_memory=True),
+                "q_dev": torch.empty((cap_queries, L), dtype=qdt, device=dev),
+                "k_dev": torch.empty(cap_queries, dtype=torch.int32, device=dev),
+                "off_dev": torch.empty(cap_queries + 1, dtype=torch.int64, device=dev),
+                "ids_dev": torch.empty(cap_entries, dtype=torch.int32, device=dev),
+                "lcp_dev": torch.empty(cap_entries, dtype=torch.int32, device=dev),
+                "ids_host": torch.empty(cap_entries, dtype=torch.int32, pin_memory=True),
+                "lcp_host": torch.empty(cap_entries, dtype=torch.int32, pin_memory=True),
+                "event": torch.cuda.Event(),
+                "batch": None,
+            }
+            self.slots.append(s)
+
+    def free_slot(self):
+        for s in self.slots:
+            if s["batch"] is None:
+                return s
+        return None
+
+    def launch(self, slot, batch: List[Request]):
+        torch = self.torch
+        nq = sum(r.b for r in batch)
+        q_np = slot["q_host"].numpy()
+        k_np = slot["k_host"].numpy()
+        off_np = slot["off_host"].numpy()
+        row = 0
+        kmax = 1
+        for r in batch:
+            qs = r.queries if r.queries.dtype != np.uint16 else r.queries.view(np.int16)
+            q_np[row:row + r.b] = qs
+            k_np[row:row + r.b] = r.k
+            kmax = max(kmax, r.k)
+            row += r.b
+        off_np[0] = 0
+        np.cumsum(k_np[:nq], out=off_np[1:nq + 1])
+        total = int(off_np[nq])
+        st = slot["stream"]
+        with torch.cuda.stream(st):
+            slot["q_dev"][:nq].copy_(slot["q_host"][:nq], non_blocking=True)
+            slot["k_dev"][:nq].copy_(slot["k_host"][:nq], non_blocking=True)
+            slot["off_dev"][:nq + 1].copy_(slot["off_host"][:nq + 1], non_blocking=True)
+            self.index.topk_dev(slot["q_dev"][:nq], slot["k_dev"], slot["off_dev"], kmax, slot["ids_dev"],
+                                slot["lcp_dev"], stream=st, scan=self.scan)
+            slot["ids_host"][:total].copy_(slot["ids_dev"][:total], non_blocking=True)
+            slot["lcp_host"][:total].copy_(slot["lcp_dev"][:total], non_blocking=True)
+            slot["event"].record(st)
+        slot["batch"] = batch
+        slot["nq"] = nq
+
+    def poll(self, now_fn) -> List[Request]:
+        done: List[Request] = []
+        for s in self.slots:
+            if s["batch"] is not None and s["event"].query():
+                t = now_fn()
+                ids = s["ids_host"].numpy()
+                lcps = s["lcp_host"].numpy()
+                pos = 0
+                for r in s["batch"]:
+                    n = r.b * r.k
+                    r.ids = ids[pos:pos + n].reshape(r.b, r.k).copy()
+                    r.lcps = lcps[pos:pos + n].reshape(r.b, r.k).copy()
+                    r.done = t
+                    pos += n
+                    done.append(r)
+                s["batch"] = None
+        return done
+
+    def busy(self) -> bool:
+        return any(s["batch"] is not None for s in self.slots)
+
+
+def run_loop(requests: List[Request], scheduler: Scheduler, executor, clock=None, max_wall_s: float = 600.0):
+    """Open-loop driver: requests are released at their arrival times; free
+    slots are refilled as soon as they drain.  Returns the completed requests.
+
+    `clock` is a callable giving seconds since the start (real time by default);
+    a fake executor may supply a virtual clock that jumps between events.
+    """
+    if clock is None:
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0  # noqa: E731
+    order = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    i = 0
+    finished: List[Request] = []
+    start = clock()
+    while i < len(order) or len(scheduler) or executor.busy():
+        now = clock()
+        while i < len(order) and order[i].arrival <= now:
+            scheduler.submit(order[i])
+            i += 1
+        while len(scheduler):
+            slot = executor.free_slot()
+            if slot is None:
+                break
+            batch = scheduler.next_batch()
+            if not batch:
+                break
+            executor.launch(slot, batch)
+        finished.extend(executor.poll(clock))
+        if clock() - start > max_wall_s:
+            raise RuntimeError("serving loop exceeded its wall-time limit")
+        if hasattr(executor, "advance"):
+            executor.advance(order[i].arrival if i < len(order) else None)
+    return finished
+
+
+def latency_report(done: List[Request], duration_s: float) -> dict:
+    lat = np.array([(r.done - r.arrival) * 1e3 for r in done])
+    nq = sum(r.b for r in done)
+    span = max(r.done for r in done) if done else 0.0
+    return {
+        "requests": len(done),
+        "queries": int(nq),
+        "offered_s": round(duration_s, 3),
+        "achieved_qps": round(nq / max(span, 1e-9), 1),
+        "p50_ms": round(float(np.percentile(lat, 50)), 4) if len(lat) else None,
+        "p99_ms": round(float(np.percentile(lat, 99)), 4) if len(lat) else None,
+        "max_ms": round(float(lat.max()), 4) if len(lat) else None,
+    }
+
+
+def requests_from_schedule(query_pool: np.ndarray, arrival_s, batch_sizes, ks) -> List[Request]:
+    """Requests for an arrival schedule; request i takes the next batch_sizes[i]
+    rows of the query pool (cycling)."""
+    reqs = []
+    pos = 0
+    n = query_pool.shape[0]
+    for i in range(len(arrival_s)):
+        b = int(batch_sizes[i])
+        sel = (np.arange(b) + pos) % n
+        pos = (pos + b) % n
+        reqs.append(Request(i, float(arrival_s[i]), query_pool[sel], int(ks[i])))
+    return reqs
+
+
+def run_served(index, requests: List[Request], n_slots: int = 3, budget_bytes: int = 1 << 30,
+               cap_queries: int = 8192, scan: bool = False) -> dict:
+    """Continuous batching over `n_slots` streams under a device-memory budget;
+    returns the latency report (requests are filled in with their answers)."""
+    row_bytes = index.L * index.token_bytes
+    kmax = max((r.k for r in requests), default=1)
+    cq, ce = slot_capacities(budget_bytes, n_slots, row_bytes, k_max=max(kmax, 1))
+    cq = min(cq, cap_queries)
+    ce = min(ce, cq * kmax)
+    ex = GpuExecutor(index, n_slots, cq, ce, scan=scan)
+    sched = Scheduler(cq, ce)
+    duration = max((r.arrival for r in requests), default=0.0)
+    done = run_loop(requests, sched, ex)
+    rep = latency_report(done, duration)
+    rep["slots"] = n_slots
+    rep["path"] = "scan" if scan else "index"
+    rep["mode"] = "continuous batching"
+    return rep
+
+
+def run_synchronous(index, requests: List[Request], scan: bool = True, max_wall_s: float = 120.0) -> dict:
+    """Baseline: one request per call, each call waited for before the next
+    (no batching, no overlap).  Requests that arrive while a call runs queue."""
+    import torch
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0  # noqa: E731
+    done = []
+    fn = index.scan_topk if scan else index.topk
+    for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
+        while clock() < r.arrival:
+            pass
+        res = fn(r.queries, r.k)
+        torch.cuda.synchronize()
+        r.ids = res.ids.cpu().numpy().reshape(r.b, r.k)
+        r.lcps = res.lcps.cpu().numpy().reshape(r.b, r.k)
+        r.done = clock()
+        done.append(r)
+        if clock() > max_wall_s:
+            break
+    duration = max((r.arrival for r in requests), default=0.0)
+    rep = latency_report(done, duration)
+    rep["path"] = "scan" if scan else "index"
+    rep["mode"] = "synchronous, one request per call"
+    rep["completed_fraction"] = round(len(done) / max(len(requests), 1), 4)
+    return rep
