@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--queries", type=int, default=8192)
     ap.add_argument("--scan-steps", type=int, default=5)
-    ap.add_argument("--scan-bw-queries", type=int, default=64,
+    ap.add_argument("--scan-bw-queries", type=int, default=32,
                     help="batch size for the scan-bandwidth measurement (HBM-bound regime)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU baseline sample")
@@ -149,7 +149,7 @@ def main():
     idx.kernel_time(2)
     idx.set_kernel_timing(False)
     row_bytes = w.L * 2
-    passes_bw = scan_passes(w.N, nbw, args.k)
+    passes_bw = idx.scan_info(nbw, args.k)[0]
     bw_bytes = w.N * row_bytes * passes_bw + nbw * row_bytes
     bw_gbs = bw_bytes / (bw_ms / bw_n * 1e-3) / 1e9
 
@@ -175,7 +175,7 @@ def main():
     idx_bytes = bytes_per_query * w.Q
     idx_gbs = idx_bytes / (k_avg_ms * 1e-3) / 1e9
     scan_kernel_ms = s_ms / max(s_n, 1)
-    passes = scan_passes(w.N, w.Q, args.k)
+    passes = idx.scan_info(w.Q, args.k)[0]
     scan_bytes = w.N * row_bytes * passes + w.Q * row_bytes
 
     # ---- serving at fixed offered load (Poisson arrivals, batches of 1-256 queries)
@@ -260,15 +260,6 @@ def served_match(reqs, ref, Q):
         if not ((r.ids == ref_ids[sel]).all() and (r.lcps == ref_lcp[sel]).all()):
             return False
     return True
-
-
-def scan_passes(N, Q, k):
-    """Number of times the full scan streams the database for a batch (one per query group)."""
-    nr = 1 if k <= 64 else 2 if k <= 128 else 4 if k <= 256 else 16
-    tq = {1: 16, 2: 8, 4: 4, 16: 1}[nr]
-    while tq > 1 and 4 * tq // 2 >= Q:
-        tq = 4 if tq > 4 else 1
-    return -(-Q // (4 * tq))
 
 
 def cpu_baseline(w, ks, args):

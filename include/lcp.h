@@ -149,6 +149,16 @@ lcp_status lcp_index_views(const lcp_index* index, const int32_t** perm, const u
                            const uint32_t** sorted_keys, const uint32_t** id_keys);
 
 /*
+ * How lcp_scan_topk would split a batch of Q queries with largest k = k_max:
+ *   query_groups : passes over the database (each group streams all rows once)
+ *   chunks       : row chunks per pass after the seed rows
+ *   seed_rows    : rows scanned first to give every query a starting limit
+ * Any output pointer may be NULL.
+ */
+lcp_status lcp_scan_info(const lcp_index* index, int64_t Q, int32_t k_max, int32_t* query_groups,
+                         int32_t* chunks, int64_t* seed_rows);
+
+/*
  * Kernel timing for benchmarks: when enabled, each query call records HIP
  * events on its stream around its main kernel (the fused index-path kernel or
  * the scan kernel).  lcp_kernel_time synchronises those events and returns

@@ -47,6 +47,7 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_index_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "lcp_index_views": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)],
+        "lcp_scan_info": [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "lcp_set_kernel_timing": [vp, i32],
         "lcp_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -189,6 +190,12 @@ class Index:
                                  (rows, r, 4 * self.N * self.row_words)):
             _hip_memcpy_d2d(dst.data_ptr(), src.value, nbytes)
         return {"perm": perm, "adj_lcp": A, "sorted_keys": srt, "id_keys": rows}
+
+    def scan_info(self, Q: int, k_max: int):
+        """Full-scan split for a batch: (query groups = passes over the rows, row chunks, seed rows)."""
+        g, c, sr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.lcp_scan_info(self._h, int(Q), int(k_max), ctypes.byref(g), ctypes.byref(c), ctypes.byref(sr)))
+        return g.value, c.value, sr.value
 
     def set_kernel_timing(self, enable: bool):
         _check(lib.lcp_set_kernel_timing(self._h, 1 if enable else 0))

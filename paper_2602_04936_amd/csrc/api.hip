@@ -53,8 +53,7 @@ struct StreamCtx {
     hipStream_t stream = nullptr;
     Slot slots[4];
     int next = 0;
-    int32_t* d_k = nullptr;
-    int64_t* d_off = nullptr;
+    void* d_kbuf = nullptr;  // [off: Q+1 int64][k: Q int32]
     size_t cap_q = 0;
     uint64_t* d_part = nullptr;
     size_t cap_part = 0;
@@ -76,6 +75,8 @@ struct lcp_index {
     uint32_t* d_sorted = nullptr;  // sorted order, key form
     int32_t* d_perm = nullptr;
     uint8_t* d_A = nullptr;
+    uint4* d_stab = nullptr;
+    int stab_levels = 0;
 
     mutable std::mutex mu;
     mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
@@ -91,6 +92,8 @@ struct lcp_index {
         v.rows = d_rows;
         v.perm = d_perm;
         v.A = d_A;
+        v.stab = d_stab;
+        v.stab_levels = stab_levels;
         v.N = N;
         v.g = g;
         return v;
@@ -104,8 +107,7 @@ void free_ctx(StreamCtx* c) {
         if (s.done) hipEventDestroy(s.done);
         if (s.host) hipHostFree(s.host);
     }
-    if (c->d_k) hipFree(c->d_k);
-    if (c->d_off) hipFree(c->d_off);
+    if (c->d_kbuf) hipFree(c->d_kbuf);
     if (c->d_part) hipFree(c->d_part);
     delete c;
 }
@@ -134,14 +136,11 @@ lcp_status get_ctx(const lcp_index* idx, hipStream_t s, StreamCtx** out) {
 lcp_status ensure_q(StreamCtx* c, size_t Q) {
     if (Q <= c->cap_q) return LCP_OK;
     size_t cap = std::max<size_t>(Q, 2 * c->cap_q);
-    HIP_TRY(hipStreamSynchronize(c->stream));  // earlier calls may still read the old buffers
-    if (c->d_k) hipFree(c->d_k);
-    if (c->d_off) hipFree(c->d_off);
-    c->d_k = nullptr;
-    c->d_off = nullptr;
+    HIP_TRY(hipStreamSynchronize(c->stream));  // earlier calls may still read the old buffer
+    if (c->d_kbuf) hipFree(c->d_kbuf);
+    c->d_kbuf = nullptr;
     c->cap_q = 0;
-    HIP_TRY(hipMalloc(&c->d_k, cap * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&c->d_off, (cap + 1) * sizeof(int64_t)));
+    HIP_TRY(hipMalloc(&c->d_kbuf, (cap + 1) * sizeof(int64_t) + cap * sizeof(int32_t)));
     c->cap_q = cap;
     return LCP_OK;
 }
@@ -170,16 +169,11 @@ hipEvent_t take_event(const lcp_index* idx) {
 }
 
 // Copy host k[] and its exclusive prefix sum to the stream's device buffers.
-lcp_status stage_k(const lcp_index* idx, StreamCtx* c, int64_t Q, const int32_t* k, int32_t* k_max_out) {
-    int32_t kmax = 1;
-    for (int64_t i = 0; i < Q; ++i) {
-        if (k[i] < 1 || k[i] > LCP_K_MAX)
-            return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
-        kmax = std::max(kmax, k[i]);
-    }
+lcp_status stage_k(StreamCtx* c, int64_t Q, const int32_t* k) {
     lcp_status st = ensure_q(c, (size_t)Q);
     if (st != LCP_OK) return st;
-    const size_t bytes = (size_t)Q * sizeof(int32_t) + (size_t)(Q + 1) * sizeof(int64_t);
+    // staging and device buffer share the layout [off: Q+1 int64][k: Q int32] of this call
+    const size_t bytes = (size_t)(Q + 1) * sizeof(int64_t) + (size_t)Q * sizeof(int32_t);
     Slot& sl = c->slots[c->next];
     c->next = (c->next + 1) % 4;
     if (sl.pending) {
@@ -198,13 +192,16 @@ lcp_status stage_k(const lcp_index* idx, StreamCtx* c, int64_t Q, const int32_t*
     off[0] = 0;
     for (int64_t i = 0; i < Q; ++i) off[i + 1] = off[i] + k[i];
     std::memcpy(kk, k, (size_t)Q * sizeof(int32_t));
-    HIP_TRY(hipMemcpyAsync(c->d_off, off, (size_t)(Q + 1) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->d_k, kk, (size_t)Q * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    // one copy: the device buffer has the same [off][k] layout as the staging slot
+    HIP_TRY(hipMemcpyAsync(c->d_kbuf, off, bytes, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipEventRecord(sl.done, c->stream));
     sl.pending = true;
-    *k_max_out = kmax;
-    (void)idx;
     return LCP_OK;
+}
+
+const int64_t* kbuf_off(const StreamCtx* c) { return static_cast<const int64_t*>(c->d_kbuf); }
+const int32_t* kbuf_k(const StreamCtx* c, int64_t Q) {
+    return reinterpret_cast<const int32_t*>(static_cast<const int64_t*>(c->d_kbuf) + Q + 1);
 }
 
 lcp_status check_query_args(const lcp_index* idx, const void* queries, int64_t Q, const void* out_ids,
@@ -223,8 +220,8 @@ constexpr int64_t kSliceIndex = 1 << 20;
 constexpr int64_t kSliceScan = 65535 * 4;
 
 lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
-                   const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp, hipStream_t s,
-                   StreamCtx* c) {
+                   const int64_t* off_dev, int32_t k_uniform, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
+                   hipStream_t s, StreamCtx* c) {
     HIP_TRY(hipSetDevice(idx->device));
     const IndexView ix = idx->view();
     const size_t row_bytes = (size_t)idx->L * idx->g.tb;
@@ -233,8 +230,10 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
         QueryBatch qb;
         qb.raw = static_cast<const uint8_t*>(queries) + (size_t)q0 * row_bytes;
         qb.Q = std::min(slice, Q - q0);
-        qb.k = k_dev + q0;
-        qb.off = off_dev + q0;
+        qb.k = k_dev ? k_dev + q0 : nullptr;
+        qb.off = off_dev ? off_dev + q0 : nullptr;
+        qb.k_uniform = k_uniform;
+        qb.q_base = q0;
         qb.k_max = k_max;
         qb.out_ids = out_ids;  // offsets are absolute
         qb.out_lcp = out_lcp;
@@ -252,7 +251,7 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
             }
         } else {
             const ScanPlan plan = plan_scan(idx->N, qb.Q, k_max);
-            lcp_status st = ensure_part(c, scan_partial_entries(plan, qb.Q, k_max));
+            lcp_status st = ensure_part(c, scan_partial_entries(plan, qb.Q, k_max, idx->g.W));
             if (st != LCP_OK) return st;
             HIP_TRY(launch_scan(ix, qb, plan, c->d_part, s, ev[0], ev[1], ev[2]));
             if (ev[0] && ev[1] && ev[2]) {
@@ -278,9 +277,18 @@ lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int6
     st = get_ctx(idx, s, &c);
     if (st != LCP_OK) return st;
     int32_t kmax = 1;
-    st = stage_k(idx, c, Q, k, &kmax);
+    bool uniform = true;
+    for (int64_t i = 0; i < Q; ++i) {
+        if (k[i] < 1 || k[i] > LCP_K_MAX)
+            return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
+        kmax = std::max(kmax, k[i]);
+        uniform = uniform && k[i] == k[0];
+    }
+    if (uniform)  // offsets are i * k: nothing to copy
+        return run_dev(idx, path, queries, Q, nullptr, nullptr, k[0], kmax, out_ids, out_lcp, s, c);
+    st = stage_k(c, Q, k);
     if (st != LCP_OK) return st;
-    return run_dev(idx, path, queries, Q, c->d_k, c->d_off, kmax, out_ids, out_lcp, s, c);
+    return run_dev(idx, path, queries, Q, kbuf_k(c, Q), kbuf_off(c), 0, kmax, out_ids, out_lcp, s, c);
 }
 
 lcp_status query_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
@@ -295,7 +303,7 @@ lcp_status query_dev(const lcp_index* idx, Path path, const void* queries, int64
     StreamCtx* c = nullptr;
     st = get_ctx(idx, s, &c);
     if (st != LCP_OK) return st;
-    return run_dev(idx, path, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, s, c);
+    return run_dev(idx, path, queries, Q, k_dev, off_dev, 0, k_max, out_ids, out_lcp, s, c);
 }
 
 struct BuildTemps {
@@ -331,6 +339,7 @@ void destroy_index(lcp_index* idx) {
     if (idx->d_sorted) hipFree(idx->d_sorted);
     if (idx->d_perm) hipFree(idx->d_perm);
     if (idx->d_A) hipFree(idx->d_A);
+    if (idx->d_stab) hipFree(idx->d_stab);
     delete idx;
 }
 
@@ -345,7 +354,9 @@ lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
     HIP_TRY(hipMalloc(&idx->d_rows, (size_t)N * W * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&idx->d_sorted, (size_t)N * W * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&idx->d_perm, (size_t)N * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&idx->d_A, (size_t)N));
+    // A is padded so that fixed-size windows around any position stay inside the allocation
+    HIP_TRY(hipMalloc(&idx->d_A, (size_t)N + kAdjPad));
+    HIP_TRY(hipMemsetAsync(idx->d_A + N, 0, kAdjPad, s));
     HIP_TRY(hipMalloc(&t.dense, (size_t)N * Wd * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&t.flags, (size_t)(1 + Wd) * sizeof(uint32_t)));
     HIP_TRY(hipMemsetAsync(t.flags, 0, (size_t)(1 + Wd) * sizeof(uint32_t), s));
@@ -357,8 +368,7 @@ lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
     if (flags[0]) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);
 
     // stable LSD radix sort of ids by the dense key: last word first, low digit first
-    const int nt = radix_tiles(N);
-    HIP_TRY(hipMalloc(&t.counts, (size_t)nt * 256 * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&t.counts, radix_counts_words(N) * sizeof(uint32_t)));
     for (int b = 0; b < 2; ++b) {
         HIP_TRY(hipMalloc(&t.keys[b], (size_t)N * sizeof(uint32_t)));
         HIP_TRY(hipMalloc(&t.vals[b], (size_t)N * sizeof(int32_t)));
@@ -382,6 +392,11 @@ lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(idx->d_perm, t.vals[cur], (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_gather_rows(idx->d_rows, idx->d_perm, N, W, idx->d_sorted, s));
     HIP_TRY(launch_adjacent_lcp(idx->d_sorted, N, g, idx->d_A, s));
+    idx->stab_levels = search_table_levels(N);
+    if (idx->stab_levels > 0) {
+        HIP_TRY(hipMalloc(&idx->d_stab, (size_t)search_table_entries(idx->stab_levels) * sizeof(uint4)));
+        HIP_TRY(launch_search_tables(idx->d_sorted, N, W, idx->stab_levels, idx->d_stab, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     return LCP_OK;
 }
@@ -462,6 +477,17 @@ lcp_status lcp_index_views(const lcp_index* idx, const int32_t** perm, const uin
     if (adj_lcp) *adj_lcp = idx->d_A;
     if (sorted_keys) *sorted_keys = idx->d_sorted;
     if (id_keys) *id_keys = idx->d_rows;
+    return LCP_OK;
+}
+
+lcp_status lcp_scan_info(const lcp_index* idx, int64_t Q, int32_t k_max, int32_t* query_groups, int32_t* chunks,
+                         int64_t* seed_rows) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (Q < 1 || k_max < 1 || k_max > LCP_K_MAX) return fail(LCP_EINVAL, "Q or k_max out of range");
+    const ScanPlan p = plan_scan(idx->N, std::min<int64_t>(Q, kSliceScan), k_max);
+    if (query_groups) *query_groups = p.qgroups;
+    if (chunks) *chunks = p.chunks;
+    if (seed_rows) *seed_rows = p.seed_rows;
     return LCP_OK;
 }
 

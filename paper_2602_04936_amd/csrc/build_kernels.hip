@@ -61,16 +61,25 @@ __global__ void k_pack_dense(const void* __restrict__ tokens, int64_t N, RowGeo 
     dense[t] = x;
 }
 
-// OR over rows of (word ^ word of row 0): the bits that vary in each dense word.
-__global__ void k_varying_bits(const uint32_t* __restrict__ dense, int64_t N, int Wd, uint32_t* __restrict__ vary) {
-    const int d = blockIdx.y;
-    uint32_t ref = dense[d];
+// OR over rows of (word ^ word of row 0): the bits that vary in each dense
+// word.  The grid has Wd * gx blocks of 256 threads, so the grid stride is a
+// multiple of Wd and every thread reads one fixed word position d of the flat
+// [N][Wd] array with coalesced loads.
+__global__ __launch_bounds__(256) void k_varying_bits(const uint32_t* __restrict__ dense, int64_t N, int Wd,
+                                                       uint32_t* __restrict__ vary) {
+    __shared__ uint32_t acc_d[128];
+    for (int i = threadIdx.x; i < Wd; i += 256) acc_d[i] = 0;
+    __syncthreads();
+    const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int d = (int)(tid % Wd);
+    const uint32_t ref = dense[d];
     uint32_t acc = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-        acc |= dense[i * Wd + d] ^ ref;
-    // wave OR reduction, then one atomic per wave (OR is order independent)
-    for (int off = 32; off > 0; off >>= 1) acc |= __shfl_xor(acc, off);
-    if (lane_id() == 0 && acc) atomicOr(&vary[d], acc);
+    for (int64_t e = tid; e < N * Wd; e += stride) acc |= dense[e] ^ ref;
+    if (acc) atomicOr(&acc_d[d], acc);  // OR is order independent
+    __syncthreads();
+    for (int i = threadIdx.x; i < Wd; i += 256)
+        if (acc_d[i]) atomicOr(&vary[i], acc_d[i]);
 }
 
 __global__ void k_iota(int32_t* __restrict__ p, int64_t N) {
@@ -111,29 +120,90 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t* __
     counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of n values by one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_exclusive(uint32_t* __restrict__ a, int64_t n) {
+// Exclusive scan of the (digit, tile) counts: per-block sums, a scan of the
+// block sums by one block, then each block scans its span and adds its base.
+constexpr int kScanSpan = 4096;  // elements per block (256 threads x 16)
+
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* wave_tot, uint32_t& total) {
+    // exclusive prefix of v over the 256 threads of the block; total = block sum
+    const int lane = lane_id();
+    const int wv = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t o = __shfl_up(x, d);
+        if (lane >= d) x += o;
+    }
+    if (lane == kWave - 1) wave_tot[wv] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t t = wave_tot[w];
+        if (w < wv) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void k_span_sums(const uint32_t* __restrict__ a, int64_t n,
+                                                   uint32_t* __restrict__ sums) {
+    __shared__ uint32_t wt[4];
+    const int64_t base = (int64_t)blockIdx.x * kScanSpan;
+    uint32_t s = 0;
+    for (int j = 0; j < kScanSpan / 256; ++j) {
+        const int64_t i = base + (int64_t)j * 256 + threadIdx.x;
+        if (i < n) s += a[i];
+    }
+    uint32_t total;
+    block_exclusive_256(s, wt, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// exclusive scan of nb block sums (one block; nb <= 1024 * 64)
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* __restrict__ sums, int nb) {
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t lo = t * per;
-    const int64_t hi = lo + per < n ? lo + per : n;
+    const int per = (nb + 1023) / 1024;
+    const int lo = t * per;
+    const int hi = lo + per < nb ? lo + per : nb;
     uint32_t s = 0;
-    for (int64_t i = lo; i < hi; ++i) s += a[i];
+    for (int i = lo; i < hi; ++i) s += sums[i];
     part[t] = s;
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 partial sums
     for (int d = 1; d < 1024; d <<= 1) {
-        uint32_t v = t >= d ? part[t - d] : 0u;
+        const uint32_t v = t >= d ? part[t - d] : 0u;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
     uint32_t run = t > 0 ? part[t - 1] : 0u;
-    for (int64_t i = lo; i < hi; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t v = sums[i];
+        sums[i] = run;
         run += v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_span_scan(uint32_t* __restrict__ a, int64_t n,
+                                                   const uint32_t* __restrict__ sums) {
+    __shared__ uint32_t wt[4];
+    // thread t owns 16 consecutive elements of the span
+    const int64_t i0 = (int64_t)blockIdx.x * kScanSpan + (int64_t)threadIdx.x * 16;
+    uint32_t v[16];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        v[j] = i0 + j < n ? a[i0 + j] : 0u;
+        s += v[j];
+    }
+    uint32_t total;
+    uint32_t run = sums[blockIdx.x] + block_exclusive_256(s, wt, total);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (i0 + j < n) a[i0 + j] = run;
+        run += v[j];
     }
 }
 
@@ -228,9 +298,85 @@ __global__ void k_adjacent_lcp(const uint32_t* __restrict__ sorted, int64_t N, R
     A[i] = (uint8_t)l;
 }
 
+static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+// ------------------------------------------------------------ search tables
+
+int search_table_levels(int64_t N) {
+    int levels = 0;
+    int64_t m = N;  // typical node size at the next level
+    while (levels < kSearchTableMaxLevels && m > kWave) {
+        ++levels;
+        m /= kWave + 1;
+    }
+    return levels;
+}
+
+int64_t search_table_entries(int levels) {
+    int64_t p = 1;
+    for (int d = 0; d < levels; ++d) p *= kWave + 1;
+    return p - 1;
+}
+
+// One thread per table entry: walk the node's path from the root (the same
+// integer arithmetic as the query's search), then store its pivot's first four
+// key words (zero past the row's end).  Entries of nodes the search never
+// reaches are zero.
+__global__ void k_search_tables(const uint32_t* __restrict__ sorted, int64_t N, int W, int levels,
+                                uint4* __restrict__ stab) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = 1;
+    for (int d = 0; d < levels; ++d) total *= kWave + 1;
+    if (t >= total - 1) return;
+    int d = 0;
+    int64_t level_start = 0, level_nodes = 1;
+    while (t >= level_start + level_nodes * kWave) {
+        level_start += level_nodes * kWave;
+        level_nodes *= kWave + 1;
+        ++d;
+    }
+    const int64_t local = t - level_start;
+    const int64_t node = local / kWave;
+    const int i = (int)(local - node * kWave);
+    int64_t lo = 0, hi = N;
+    int64_t rest = node, div = level_nodes / (kWave + 1);
+    bool reachable = true;
+    for (int e = 0; e < d; ++e) {  // digits of `node` in base 65, most significant first
+        const int64_t n = hi - lo;
+        if (n <= kWave) {
+            reachable = false;
+            break;
+        }
+        const int c = (int)(rest / div);
+        rest -= (int64_t)c * div;
+        div /= kWave + 1;
+        const int64_t left = c > 0 ? lo + ((int64_t)c * n) / (kWave + 1) + 1 : lo;
+        const int64_t right = c < kWave ? lo + ((int64_t)(c + 1) * n) / (kWave + 1) : hi;
+        lo = left;
+        hi = right;
+    }
+    uint4 key = make_uint4(0u, 0u, 0u, 0u);
+    if (reachable && hi - lo > kWave) {
+        const int64_t pos = lo + ((int64_t)(i + 1) * (hi - lo)) / (kWave + 1);
+        const uint32_t* r = sorted + pos * W;
+        key.x = r[0];
+        key.y = W > 1 ? r[1] : 0u;
+        key.z = W > 2 ? r[2] : 0u;
+        key.w = W > 3 ? r[3] : 0u;
+    }
+    stab[t] = key;
+}
+
 // ------------------------------------------------------------ launchers
 
-static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
+                                hipStream_t s) {
+    const int64_t n = search_table_entries(levels);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_search_tables, dim3(blocks_for(n, 256)), dim3(256), 0, s, sorted, N, W, levels, stab);
+    return hipGetLastError();
+}
+
 
 hipError_t launch_pack(const void* tokens, int64_t N, RowGeo g, uint32_t V, int dbits, int Wd, uint32_t* keys,
                        uint32_t* dense, uint32_t* bad, hipStream_t s) {
@@ -240,13 +386,19 @@ hipError_t launch_pack(const void* tokens, int64_t N, RowGeo g, uint32_t V, int 
 }
 
 hipError_t launch_varying_bits(const uint32_t* dense, int64_t N, int Wd, uint32_t* vary, hipStream_t s) {
-    unsigned gx = blocks_for(N, 256);
-    if (gx > 1024) gx = 1024;
-    hipLaunchKernelGGL(k_varying_bits, dim3(gx, (unsigned)Wd), dim3(256), 0, s, dense, N, Wd, vary);
+    // Wd <= 128; grid = Wd * gx blocks keeps the grid stride a multiple of Wd
+    int64_t gx = (N + 255) / 256;
+    if (gx > 2048 / Wd + 1) gx = 2048 / Wd + 1;
+    hipLaunchKernelGGL(k_varying_bits, dim3((unsigned)(gx * Wd)), dim3(256), 0, s, dense, N, Wd, vary);
     return hipGetLastError();
 }
 
 int radix_tiles(int64_t N) { return (int)((N + kTile - 1) / kTile); }
+
+size_t radix_counts_words(int64_t N) {
+    const int64_t n = (int64_t)radix_tiles(N) * 256;
+    return (size_t)(n + (n + kScanSpan - 1) / kScanSpan);
+}
 
 hipError_t launch_iota(int32_t* p, int64_t N, hipStream_t s) {
     hipLaunchKernelGGL(k_iota, dim3(blocks_for(N, 256)), dim3(256), 0, s, p, N);
@@ -263,7 +415,12 @@ hipError_t launch_radix_pass(const uint32_t* keys_in, const int32_t* vals_in, in
                              uint32_t* keys_out, int32_t* vals_out, bool write_keys, hipStream_t s) {
     const int nt = radix_tiles(N);
     hipLaunchKernelGGL(k_radix_hist, dim3(nt), dim3(kRadixThreads), 0, s, keys_in, N, shift, counts, nt);
-    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, s, counts, (int64_t)nt * 256);
+    const int64_t n = (int64_t)nt * 256;
+    const int nb = (int)((n + kScanSpan - 1) / kScanSpan);
+    uint32_t* sums = counts + n;  // the counts buffer has room for the block sums
+    hipLaunchKernelGGL(k_span_sums, dim3(nb), dim3(256), 0, s, counts, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_span_scan, dim3(nb), dim3(256), 0, s, counts, n, sums);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nt), dim3(kRadixThreads), 0, s, keys_in, vals_in, N, shift, counts, nt,
                        keys_out, vals_out, write_keys ? 1 : 0);
     return hipGetLastError();

@@ -70,6 +70,17 @@ __device__ __forceinline__ int wave_prefix_min(int v) {
     return v;
 }
 
+// minimum over the wave's lanes (every lane gets it)
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ d) << 2, (int)v);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------- rows
 //
 // Key form: a row of L tokens of `tb` bytes is stored as W = ceil(L*tb/4)
@@ -176,6 +187,43 @@ __device__ __forceinline__ uint64_t rank_key(int lcp, uint32_t id) {
 __device__ __forceinline__ int key_lcp(uint64_t k) { return 255 - (int)(k >> 32); }
 __device__ __forceinline__ int key_id(uint64_t k) { return (int)(uint32_t)k; }
 
+// ---------------------------------------------------------------- wave sorting
+
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, int mask) {
+    const int src = lane_id() ^ mask;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t reverse_lanes64(uint64_t v) { return xor_lane64(v, kWave - 1); }
+
+// Ascending bitonic sort of one key per lane.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t y = xor_lane64(x, stride);
+            const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+            x = keep_min ? (x < y ? x : y) : (x > y ? x : y);
+        }
+    }
+    return x;
+}
+
+// Sort a bitonic sequence held one key per lane into ascending order.
+__device__ __forceinline__ uint64_t wave_bitonic_clean64(uint64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int stride = kWave / 2; stride > 0; stride >>= 1) {
+        const uint64_t y = xor_lane64(x, stride);
+        x = (lane & stride) == 0 ? (x < y ? x : y) : (x > y ? x : y);
+    }
+    return x;
+}
+
 // ---------------------------------------------------------------- sorted list
 //
 // Ascending list of up to 64*NR keys spread over the wave: entry e lives in
@@ -217,13 +265,33 @@ struct WaveList {
         }
     }
 
+    // Merge one ascending key per lane into the list (64*NR smallest kept):
+    // register by register, the bitonic split of (list register, reversed
+    // carry) keeps the 64 smaller keys and carries the 64 larger ones on.
+    __device__ __forceinline__ void merge_sorted(uint64_t sorted) {
+        uint64_t carry = sorted;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint64_t rc = reverse_lanes64(carry);
+            const uint64_t lo = v[r] < rc ? v[r] : rc;
+            const uint64_t hi = v[r] < rc ? rc : v[r];
+            v[r] = wave_bitonic_clean64(lo);
+            if (r + 1 < NR) carry = wave_bitonic_clean64(hi);
+        }
+    }
+
     // Offer every lane's key where `pass` holds; afterwards entries [0, m)
     // are the m smallest keys among the previous entries and the offers.
+    // Few offers are inserted one by one, many are sorted and merged at once.
     __device__ __forceinline__ void offer(uint64_t key, bool pass, int m) {
         const int lane = lane_id();
         uint64_t thr = get(m - 1);
         pass = pass && key < thr;
         uint64_t bal = ballot(pass);
+        if (popc64(bal) > 6) {
+            merge_sorted(wave_sort64(pass ? key : kKeyMax));
+            return;
+        }
         while (bal) {
             const int src = low_lane(bal);
             insert(readlane64(key, src));

@@ -13,6 +13,7 @@ hipError_t launch_pack(const void* tokens, int64_t N, RowGeo g, uint32_t V, int 
                        uint32_t* dense, uint32_t* bad, hipStream_t s);
 hipError_t launch_varying_bits(const uint32_t* dense, int64_t N, int Wd, uint32_t* vary, hipStream_t s);
 int radix_tiles(int64_t N);
+size_t radix_counts_words(int64_t N);  // counts + block sums for one radix pass
 hipError_t launch_iota(int32_t* p, int64_t N, hipStream_t s);
 hipError_t launch_gather_word(const uint32_t* dense, const int32_t* perm, int64_t N, int Wd, int d, uint32_t* keys,
                               hipStream_t s);
@@ -22,12 +23,29 @@ hipError_t launch_gather_rows(const uint32_t* keys, const int32_t* perm, int64_t
                               hipStream_t s);
 hipError_t launch_adjacent_lcp(const uint32_t* sorted, int64_t N, RowGeo g, uint8_t* A, hipStream_t s);
 
+hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
+                                hipStream_t s);
+
 // ---- queries
+constexpr int kAdjWindow = 1024;                  // bytes of A one query wave stages in LDS
+constexpr size_t kAdjPad = kAdjWindow + 64;       // zero bytes allocated past A[N-1]
+
+// Search tables: the top `levels` levels of the static 65-ary search tree over
+// [0, N).  A node with range [lo, hi), n = hi - lo > 64, has pivots
+// lo + (i+1)*n/65 (i < 64) and children [lo, p0), [p0+1, p1), ..., [p63+1, hi).
+// Level d holds 65^d nodes of 64 entries starting at entry 65^d - 1; an entry
+// is the pivot row's first four key words (zero past the row's end).
+constexpr int kSearchTableMaxLevels = 3;
+int search_table_levels(int64_t N);
+int64_t search_table_entries(int levels);  // 65^levels - 1
+
 struct IndexView {
     const uint32_t* sorted;  // [N][W] key form, lexicographic order
     const uint32_t* rows;    // [N][W] key form, id order
     const int32_t* perm;     // [N]
     const uint8_t* A;        // [N] adjacent LCP
+    const uint4* stab;       // search tables (may be null when levels == 0)
+    int stab_levels;
     int64_t N;
     RowGeo g;
 };
@@ -35,25 +53,37 @@ struct IndexView {
 struct QueryBatch {
     const void* raw;         // [Q][L] raw tokens (tb bytes each)
     int64_t Q;
-    const int32_t* k;        // [Q] device
-    const int64_t* off;      // [Q+1] device
+    const int32_t* k;        // [Q] device (unused when k_uniform > 0)
+    const int64_t* off;      // [Q+1] device (unused when k_uniform > 0)
+    int32_t k_uniform;       // > 0: every query has this k and query i starts at (q_base + i) * k
+    int64_t q_base;          // absolute index of this slice's first query
     int32_t k_max;
     int32_t* out_ids;
     int32_t* out_lcp;
 };
 
+__device__ __forceinline__ int query_k(const QueryBatch& qb, int64_t qi) {
+    return qb.k_uniform > 0 ? qb.k_uniform : qb.k[qi];
+}
+__device__ __forceinline__ int64_t query_off(const QueryBatch& qb, int64_t qi) {
+    return qb.k_uniform > 0 ? (qb.q_base + qi) * (int64_t)qb.k_uniform : qb.off[qi];
+}
+
 hipError_t launch_index_query(const IndexView& ix, const QueryBatch& qb, hipStream_t s);
 
 // Full scan.  `part` must hold scan_partial_entries(...) keys.
 struct ScanPlan {
-    int tq;        // queries per wave
-    int nr;        // list registers (capacity 64*nr >= k_max)
-    int chunks;    // row chunks (grid x)
-    int qgroups;   // query groups (grid y), 4*tq queries each
+    int tq;             // queries per wave
+    int nr;             // list registers (capacity 64*nr >= k_max)
+    int chunks;         // row chunks after the seed rows (grid x)
+    int qgroups;        // query groups (grid y), 4*tq queries each
+    int nparts;         // partial lists per query (seed chunks + chunks)
+    int seed_chunks;    // chunks of rows [0, seed_rows) scanned first to seed the limits
+    int64_t seed_rows;
     int64_t chunk_rows;
 };
 ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max);
-size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max);
+size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, int W);  // in 8-byte units
 hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* part, hipStream_t s,
                        hipEvent_t ev_scan0, hipEvent_t ev_scan1, hipEvent_t ev_merge1);
 

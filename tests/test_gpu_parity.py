@@ -186,3 +186,76 @@ def test_errors(P):
     assert r.ids.numel() == 0
     idx.close()
     torch.cuda.synchronize()
+
+
+def test_uniform_and_mixed_k_agree(P):
+    """Uniform k (offsets computed on the device) and per-query k (staged
+    offsets) give the same per-query answers."""
+    import torch
+    w = synth.c3_like(100_000, 300, seed=9)
+    with P.Index(w.db, w.V) as idx:
+        for kval in (1, 10, 64, 65, 100):
+            a = idx.topk(w.queries, kval)
+            ks = np.full(w.Q, kval, np.int32)
+            ks[0] = 1 if kval != 1 else 2  # force the staged path
+            b = idx.topk(w.queries, ks)
+            s = idx.scan_topk(w.queries, kval)
+            torch.cuda.synchronize()
+            assert torch.equal(a.ids, s.ids) and torch.equal(a.lcps, s.lcps)
+            for qi in range(1, w.Q):
+                x, y = a.query(qi)
+                u, v = b.query(qi)
+                assert torch.equal(x, u) and torch.equal(y, v)
+        wi, wl, _ = oracle.c_topk(w.db, w.queries, 10)
+        a = idx.topk(w.queries, 10)
+        torch.cuda.synchronize()
+        assert (a.ids.cpu().numpy() == wi).all() and (a.lcps.cpu().numpy() == wl).all()
+
+
+def test_device_k_entry_points(P):
+    import torch
+    w = synth.c1_tiny()
+    rng = np.random.default_rng(3)
+    ks = rng.integers(1, 80, w.Q).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    wi, wl, _ = O.topk_batch(w.db, w.queries, ks)
+    with P.Index(w.db, w.V) as idx:
+        q = P.to_device_tokens(w.queries)
+        kd = torch.from_numpy(ks).cuda()
+        od = torch.from_numpy(off).cuda()
+        for scan in (False, True):
+            ids = torch.full((int(off[-1]),), -7, dtype=torch.int32, device="cuda")
+            lcps = torch.full_like(ids, -7)
+            idx.topk_dev(q, kd, od, int(ks.max()), ids, lcps, scan=scan)
+            torch.cuda.synchronize()
+            assert (ids.cpu().numpy() == wi).all() and (lcps.cpu().numpy() == wl).all()
+
+
+def test_groups_far_beyond_the_staged_window(P):
+    """Skewed data: 90% of rows share a 12-token prefix, so the groups around
+    most queries span tens of thousands of sorted positions."""
+    rng = np.random.default_rng(21)
+    N, L = 120_000, 24
+    db = synth.random_rows(rng, N, L, 4)
+    hot = rng.random(N) < 0.9
+    db[hot, :12] = 1
+    qs = synth.random_rows(rng, 40, L, 4)
+    qs[:30, :12] = 1
+    qs[10:20, 12:] = db[hot][:10, 12:]
+    ks = np.array([1, 10, 100, 1000] * 10, dtype=np.int32)
+    check_against_oracle(P, db, qs, ks, 4, "skewed long groups")
+
+
+def test_served_results_equal_alone(P):
+    """Continuous batching on the GPU: every request's answer equals the
+    oracle's answer for that request alone."""
+    from paper_2602_04936_amd import serve
+    w = synth.c3_like(200_000, 2000, seed=4)
+    t, b, k = synth.serving_schedule(20000, 0.5, seed=5, k_mode="uniform")
+    with P.Index(w.db, w.V) as idx:
+        reqs = serve.requests_from_schedule(w.queries, t, b, k)
+        rep = serve.run_served(idx, reqs, n_slots=3)
+    assert rep["requests"] == len(reqs)
+    for r in reqs[:: max(1, len(reqs) // 60)]:
+        wi, wl, _ = oracle.c_topk(w.db, r.queries, r.k)
+        assert (r.ids.reshape(-1) == wi).all() and (r.lcps.reshape(-1) == wl).all(), r.rid
