@@ -169,7 +169,9 @@ def main():
     except Exception as e:  # the oracle is a test dependency; report, do not fail the bench
         parity = {"error": repr(e)}
 
-    # ---- roofline of the index-path kernel (algorithmic bytes: see the design doc)
+    # ---- roofline of the index-path kernel: the bytes a comparison-based search
+    # must move per query (query row + ceil(log2(N+1)) probed rows), plus the
+    # perm id and adjacent-LCP byte of each answer and the 8-byte output entry
     probes = int(np.ceil(np.log2(w.N + 1)))
     bytes_per_query = row_bytes + probes * row_bytes + args.k * (4 + 1) + args.k * 8
     idx_bytes = bytes_per_query * w.Q
