@@ -42,6 +42,12 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="duration of each fixed-rate serving run (0 disables)")
     ap.add_argument("--serve-rates", type=str, default="10000,100000")
+    ap.add_argument("--no-uneven", dest="uneven", action="store_false",
+                    help="skip the uneven-k batch comparison")
+    ap.add_argument("--sensor-steps", type=int, default=5000,
+                    help="steps of the sensor-fusion stream (0 disables)")
+    ap.add_argument("--energy-seconds", type=float, default=1.0,
+                    help="sustained run per energy reading (0 disables the energy section)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain 1-byte elementwise copy of this size (profiler counter calibration)")
     ap.add_argument("--quiet", action="store_true")
@@ -91,13 +97,17 @@ def main():
     for _ in range(args.warmup):
         idx.topk(q_dev, ks, out=(ids, lcps))
     torch.cuda.synchronize()
-    idx.set_kernel_timing(True)
-    idx.kernel_time(0)
     t1 = time.perf_counter()
     for _ in range(args.steps):
         idx.topk(q_dev, ks, out=(ids, lcps))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
+    # kernel duration from HIP events on the library's stream, in a second pass
+    # of the same steps so that the events do not sit inside the timed region
+    idx.set_kernel_timing(True)
+    idx.kernel_time(0)
+    for _ in range(args.steps):
+        idx.topk(q_dev, ks, out=(ids, lcps))
     kms, kn = idx.kernel_time(0)
     idx.set_kernel_timing(False)
     ms_per_step = dt * 1e3 / args.steps
@@ -197,6 +207,111 @@ def main():
             rep = serve.run_synchronous(idx, reqs, scan=True, max_wall_s=2 * args.serve_seconds + 5)
             serving["scan_synchronous"][str(int(rate))] = rep
             log(args, f"[bench] synchronous full scan @{int(rate)}/s: {rep}")
+            t, b, kk = synth.serving_schedule(rate, args.serve_seconds, seed=1004, k_mode="uniform")
+            reqs = serve.requests_from_schedule(w.queries, t, b, kk)
+            rep = serve.run_served(idx, reqs)
+            serving.setdefault("index_continuous_batching_k_uniform_1_100", {})[str(int(rate))] = rep
+            log(args, f"[bench] served index path, k uniform 1..100 @{int(rate)}/s: {rep}")
+
+    # ---- uneven batch: the same 8,192 queries with k uniform on {1, 10, 100}:
+    # one plain launch, per-k-bucket plain launches, and one persistent launch
+    # replayed from a captured HIP graph with the autotuned grid
+    uneven = None
+    if args.uneven:
+        from paper_2602_04936_amd import batching
+        ku = synth.uneven_k(w.Q)
+        buckets = batching.split_by_k(ku)
+        bq = {kv: q_dev[torch.from_numpy(sel).to(dev)] for kv, sel in buckets.items()}
+        bout = {kv: (torch.empty(len(sel) * kv, dtype=torch.int32, device=dev),
+                     torch.empty(len(sel) * kv, dtype=torch.int32, device=dev)) for kv, sel in buckets.items()}
+        uo = (torch.empty(int(ku.sum()), dtype=torch.int32, device=dev),
+              torch.empty(int(ku.sum()), dtype=torch.int32, device=dev))
+        tune = batching.tune_launch(idx, q_dev, ku, reps=5)
+        cl = batching.CapturedLaunch(idx, cap_queries=w.Q, k_max=100, blocks=tune["best"].blocks
+                                     if tune["best"].mode == "persistent" else 0)
+
+        def timed(fn, reps=20):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3 / reps
+
+        one = timed(lambda: idx.topk(q_dev, ku, out=uo))
+        per_bucket = timed(lambda: [idx.topk(bq[kv], kv, out=bout[kv]) for kv in buckets])
+        captured = timed(lambda: cl.run(q_dev, ku))
+        ref = idx.topk(q_dev, ku, out=uo)
+        gi, gl, _ = cl.run(q_dev, ku)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(gi, ref.ids) and torch.equal(gl, ref.lcps))
+        uneven = {"queries": w.Q, "k_choices": [1, 10, 100],
+                  "one_plain_launch_ms": round(one, 4), "per_k_bucket_launches_ms": round(per_bucket, 4),
+                  "captured_persistent_ms": round(captured, 4),
+                  "captured_persistent_qps": round(w.Q / (captured * 1e-3), 1),
+                  "autotune": [(sh.mode, sh.blocks, round(sh.ms, 4)) for sh in tune["tried"]],
+                  "captured_equals_plain": same}
+        log(args, f"[bench] uneven batch: {uneven}")
+
+    # ---- energy per query from the socket energy accumulator: idle draw, the
+    # index path, the full scan, and full scans over the first N/B rows (the
+    # bucket-count sweep: a query confined to one of B equal prefix buckets
+    # scans N/B rows)
+    energy = None
+    if args.energy_seconds > 0:
+        from paper_2602_04936_amd import energy as E
+        meter, why = E.try_meter(dev)
+        if meter is None:
+            energy = {"unavailable": why}
+        else:
+            es = args.energy_seconds
+            energy = {"idle_watts": round(meter.idle_watts(min(es, 0.5)), 1)}
+
+            def run_index():
+                idx.topk(q_dev, ks, out=(ids, lcps))
+                return w.Q
+
+            def run_scan(ix):
+                def f():
+                    ix.scan_topk(q_dev, ks, out=(sids, slcp))
+                    return w.Q
+                return f
+
+            energy["index"] = meter.measure(run_index, es, sync_every=64)
+            energy["full_scan"] = meter.measure(run_scan(idx), es, sync_every=1)
+            sweep = {"1": energy["full_scan"]["j_per_query"]}
+            for B in (4, 16, 64, 256):
+                n = w.N // B
+                sub = P.Index(P.to_device_tokens(w.db[:n], dev), w.V)
+                sweep[str(B)] = meter.measure(run_scan(sub), es / 2, sync_every=4)["j_per_query"]
+                sub.close()
+            energy["scan_j_per_query_vs_buckets"] = sweep
+            energy["index_vs_full_scan_energy_ratio"] = round(
+                energy["full_scan"]["j_per_query"] / energy["index"]["j_per_query"], 1)
+            meter.close()
+        log(args, f"[bench] energy: {energy}")
+
+    # ---- sensor-fusion stream: N=1M history, 1,000 queries per step (k=5) at a
+    # 4,000 Hz target, that step's 1,000 readings appended every 1,000 steps
+    sensor = None
+    if args.sensor_steps > 0:
+        from paper_2602_04936_amd import serve
+        st = synth.SensorStream(seed=1005)
+        hist = np.concatenate(list(st.steps(1000)), axis=0)
+        sidx = P.Index(hist, synth.SensorStream.V)
+
+        def append(index, batch):
+            index.append(batch)
+            return index
+
+        rep = serve.run_step_stream(sidx, st.steps(args.sensor_steps), rate_hz=4000.0, k=5, append_every=1000,
+                                    append=append)
+        rep["final_rows"] = rep.pop("index").N
+        sidx.close()
+        rep["append_mode"] = "lcp_index_append (sorted merge)"
+        sensor = rep
+        log(args, f"[bench] sensor stream: {sensor}")
 
     # ---- CPU baseline: the oracle as it is, on a bounded sample
     cpu = None
@@ -230,7 +345,8 @@ def main():
                    "path": "index (lcp_topk)", "parallelism": "single GPU"},
         "roofline": {"kernel": "k_index_query", "bound": "hbm", "achieved": round(idx_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(idx_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_kernel_us": round(k_avg_ms * 1e3, 2),
+                     "traffic": measured_traffic(w.Q, args.k), "traffic_unit": "bytes per launch",
+                     "avg_kernel_us": round(k_avg_ms * 1e3, 2),
                      "algorithmic_bytes_per_query": bytes_per_query},
         "scan": {"qps": round(scan_qps, 1), "ms_per_batch": round(sdt * 1e3 / args.scan_steps, 4),
                  "index_speedup": round(qps / scan_qps, 2), "scan_kernel_ms": round(scan_kernel_ms, 4),
@@ -243,11 +359,38 @@ def main():
                           "avg_kernel_us": round(bw_ms / bw_n * 1e3, 2)},
         "build_ms": round(build_ms, 2),
         "serving": serving,
+        "uneven_batch": uneven,
+        "sensor_stream": sensor,
+        "energy": energy,
         "parity": parity,
         "cpu_baseline": cpu,
     }
     idx.close()
     print(json.dumps(out), flush=True)
+
+
+INDEX_KERNEL_SOURCES = ("query_kernels.hip", "device.hpp", "launch.hpp")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_c3_index_and_scan.md")
+
+
+def measured_traffic(queries, k):
+    """HBM bytes per index-path launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken (or the
+    workload differs)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic k_index_query bytes_per_launch=(\d+) queries=(\d+) k=(\d+) \S+ sha256=([0-9a-f]+)", text)
+    if not m or int(m.group(2)) != queries or int(m.group(3)) != k:
+        return None
+    h = hashlib.sha256()
+    for f in INDEX_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2602_04936_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m.group(1)) if h.hexdigest() == m.group(4) else None
 
 
 def served_match(reqs, ref, Q):

@@ -123,6 +123,44 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
                              const int32_t* k_dev, const int64_t* off_dev, int32_t k_max,
                              int32_t* out_ids, int32_t* out_lcp, void* stream);
 
+/*
+ * Append n rows to an index; they get ids N, N+1, ..., N+n-1.  Afterwards the
+ * index is identical (sorted order, adjacent LCP, answers) to one built over
+ * the concatenated rows.  The paper lists dynamic insertion as future work
+ * (section "Limitations"); this is the sorted-order merge: the new rows are
+ * sorted, placed after equal old rows (their ids are larger), and the
+ * adjacent-LCP array and search tables are recomputed.
+ *
+ *   tokens : device, [n][L], same width as the index; every token < V.
+ *   n      : 0 <= n, N + n < 2^31 (n = 0 is a no-op).
+ *   stream : the call first synchronises every stream the index has been used
+ *            on, then runs on `stream` and synchronises it before returning.
+ *            No query may run on the index during the call.
+ * Errors: LCP_EINVAL, LCP_ERANGE (a token >= V; the index is unchanged),
+ * LCP_ENOMEM, LCP_EDEVICE.
+ */
+lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, void* stream);
+
+/*
+ * Persistent, graph-capturable form of lcp_topk_dev for batches of uneven
+ * size and k: one launch of `blocks` workgroups (4 waves each; blocks <= 0
+ * picks one that fills the device) whose waves take queries from a device
+ * work counter until *q_count_dev queries are done.  The batch size is read
+ * on the device, so a HIP graph captured once replays for any batch up to the
+ * capacity of the buffers it was captured with.  Answers are those of
+ * lcp_topk_dev (bit-identical; the order in which waves take queries does not
+ * reach the output).
+ *
+ *   q_count_dev : device int64, number of queries of this launch (0..Q_cap).
+ *   k_dev, off_dev, k_max : as lcp_topk_dev (k_max bounds every k of any
+ *                 batch replayed through a captured graph).
+ * Capture: make one call on the stream first (it sets up the stream's work
+ * counter); the call itself allocates nothing and never synchronises.
+ */
+lcp_status lcp_topk_persistent(const lcp_index* index, const void* queries, const int64_t* q_count_dev,
+                               const int32_t* k_dev, const int64_t* off_dev, int32_t k_max, int32_t* out_ids,
+                               int32_t* out_lcp, int32_t blocks, void* stream);
+
 /* Synchronise every stream the index has been used on, then free it.  NULL is a no-op. */
 void lcp_index_free(lcp_index* index);
 

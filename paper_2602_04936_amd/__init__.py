@@ -48,6 +48,8 @@ def _load_lib() -> ctypes.CDLL:
                            ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "lcp_index_views": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)],
         "lcp_scan_info": [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)],
+        "lcp_index_append": [vp, vp, i64, vp],
+        "lcp_topk_persistent": [vp, vp, vp, vp, vp, i32, vp, vp, i32, vp],
         "lcp_set_kernel_timing": [vp, i32],
         "lcp_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -174,6 +176,29 @@ class Index:
         fn = lib.lcp_scan_topk_dev if scan else lib.lcp_topk_dev
         _check(fn(self._h, q.data_ptr(), q.shape[0], k_dev.data_ptr(), off_dev.data_ptr(), int(k_max),
                   out_ids.data_ptr(), out_lcp.data_ptr(), _stream_handle(stream)))
+
+    def topk_persistent(self, queries: torch.Tensor, q_count_dev: torch.Tensor, k_dev: torch.Tensor,
+                        off_dev: torch.Tensor, k_max: int, out_ids: torch.Tensor, out_lcp: torch.Tensor,
+                        blocks: int = 0, stream=None):
+        """Persistent, graph-capturable launch (lcp_topk_persistent); the batch size is *q_count_dev."""
+        q = _token_tensor(queries, self.token_bytes)
+        if q_count_dev.dtype != torch.int64 or k_dev.dtype != torch.int32 or off_dev.dtype != torch.int64:
+            raise TypeError("q_count_dev and off_dev must be int64, k_dev int32")
+        _check(lib.lcp_topk_persistent(self._h, q.data_ptr(), q_count_dev.data_ptr(), k_dev.data_ptr(),
+                                       off_dev.data_ptr(), int(k_max), out_ids.data_ptr(), out_lcp.data_ptr(),
+                                       int(blocks), _stream_handle(stream)))
+
+    def append(self, tokens, stream=None):
+        """Append rows (ids N, N+1, ...); the index then equals a build over the concatenation."""
+        if isinstance(tokens, np.ndarray):
+            tokens = to_device_tokens(tokens, self.device)
+        t = _token_tensor(tokens, self.token_bytes)
+        if t.shape[1] != self.L:
+            raise ValueError(f"rows have L={t.shape[1]}, index has L={self.L}")
+        _check(lib.lcp_index_append(self._h, t.data_ptr(), t.shape[0], _stream_handle(stream)))
+        n = ctypes.c_int64()
+        _check(lib.lcp_index_info(self._h, ctypes.byref(n), None, None, None, None))
+        self.N = n.value
 
     # ------------------------------------------------------------- tooling
     def views(self):

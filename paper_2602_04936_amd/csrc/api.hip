@@ -57,6 +57,7 @@ struct StreamCtx {
     size_t cap_q = 0;
     uint64_t* d_part = nullptr;
     size_t cap_part = 0;
+    unsigned long long* d_counter = nullptr;  // persistent launches' work counter
 };
 
 struct TimedLaunch {
@@ -68,6 +69,7 @@ struct TimedLaunch {
 
 struct lcp_index {
     int device = 0;
+    int cus = 0;  // compute units of the device
     int64_t N = 0;
     int32_t L = 0, V = 0;
     RowGeo g{};
@@ -77,6 +79,7 @@ struct lcp_index {
     uint8_t* d_A = nullptr;
     uint4* d_stab = nullptr;
     int stab_levels = 0;
+    uint32_t* d_bmin = nullptr;
 
     mutable std::mutex mu;
     mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
@@ -94,6 +97,7 @@ struct lcp_index {
         v.A = d_A;
         v.stab = d_stab;
         v.stab_levels = stab_levels;
+        v.bmin = d_bmin;
         v.N = N;
         v.g = g;
         return v;
@@ -109,6 +113,7 @@ void free_ctx(StreamCtx* c) {
     }
     if (c->d_kbuf) hipFree(c->d_kbuf);
     if (c->d_part) hipFree(c->d_part);
+    if (c->d_counter) hipFree(c->d_counter);
     delete c;
 }
 
@@ -340,65 +345,148 @@ void destroy_index(lcp_index* idx) {
     if (idx->d_perm) hipFree(idx->d_perm);
     if (idx->d_A) hipFree(idx->d_A);
     if (idx->d_stab) hipFree(idx->d_stab);
+    if (idx->d_bmin) hipFree(idx->d_bmin);
     delete idx;
+}
+
+// Key-form rows (id order) of n raw token rows and their stable lexicographic
+// order (perm over local ids 0..n-1).  LCP_ERANGE if a token is >= V.
+lcp_status sort_rows(const void* tokens, int64_t n, const RowGeo& g, int32_t V, hipStream_t s, uint32_t* keys_out,
+                     int32_t* perm_out) {
+    int dbits = 1;
+    while ((1 << dbits) < V && dbits < 16) ++dbits;
+    const int Wd = (g.L * dbits + 31) / 32;
+    BuildTemps t;
+    HIP_TRY(hipMalloc(&t.dense, (size_t)n * Wd * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&t.flags, (size_t)(1 + Wd) * sizeof(uint32_t)));
+    HIP_TRY(hipMemsetAsync(t.flags, 0, (size_t)(1 + Wd) * sizeof(uint32_t), s));
+    HIP_TRY(launch_pack(tokens, n, g, (uint32_t)V, dbits, Wd, keys_out, t.dense, t.flags, s));
+    HIP_TRY(launch_varying_bits(t.dense, n, Wd, t.flags + 1, s));
+    std::vector<uint32_t> flags(1 + Wd);
+    HIP_TRY(hipMemcpyAsync(flags.data(), t.flags, flags.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flags[0]) return fail(LCP_ERANGE, "a token is >= V = %d", V);
+
+    // stable LSD radix sort of ids by the dense key: last word first, low digit first
+    HIP_TRY(hipMalloc(&t.counts, radix_counts_words(n) * sizeof(uint32_t)));
+    for (int b = 0; b < 2; ++b) {
+        HIP_TRY(hipMalloc(&t.keys[b], (size_t)n * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&t.vals[b], (size_t)n * sizeof(int32_t)));
+    }
+    int cur = 0;
+    HIP_TRY(launch_iota(t.vals[cur], n, s));
+    for (int d = Wd - 1; d >= 0; --d) {
+        const uint32_t vary = flags[1 + d];
+        if (!vary) continue;
+        HIP_TRY(launch_gather_word(t.dense, t.vals[cur], n, Wd, d, t.keys[cur], s));
+        int last_digit = -1;
+        for (int dg = 0; dg < 4; ++dg)
+            if ((vary >> (8 * dg)) & 0xFFu) last_digit = dg;
+        for (int dg = 0; dg < 4; ++dg) {
+            if (!((vary >> (8 * dg)) & 0xFFu)) continue;
+            HIP_TRY(launch_radix_pass(t.keys[cur], t.vals[cur], n, 8 * dg, t.counts, t.keys[cur ^ 1],
+                                      t.vals[cur ^ 1], dg != last_digit, s));
+            cur ^= 1;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(perm_out, t.vals[cur], (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the temporaries are freed on return
+    return LCP_OK;
+}
+
+// A, search tables (sorted rows and perm in place)
+lcp_status finish_index(lcp_index* idx, hipStream_t s) {
+    const int64_t N = idx->N;
+    HIP_TRY(launch_adjacent_lcp(idx->d_sorted, N, idx->g, idx->d_A, s));
+    idx->stab_levels = search_table_levels(N);
+    if (idx->stab_levels > 0) {
+        HIP_TRY(hipMalloc(&idx->d_stab, (size_t)search_table_entries(idx->stab_levels) * sizeof(uint4)));
+        HIP_TRY(launch_search_tables(idx->d_sorted, N, idx->g.W, idx->stab_levels, idx->d_stab, s));
+    }
+    HIP_TRY(hipMalloc(&idx->d_bmin, (size_t)block_min_entries(N) * sizeof(uint32_t)));
+    HIP_TRY(launch_block_min(idx->d_perm, N, idx->d_bmin, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return LCP_OK;
 }
 
 lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
     const int64_t N = idx->N;
-    const RowGeo g = idx->g;
-    const int W = g.W;
-    int dbits = 1;
-    while ((1 << dbits) < idx->V && dbits < 16) ++dbits;
-    const int Wd = (idx->L * dbits + 31) / 32;
-    BuildTemps t;
+    const int W = idx->g.W;
     HIP_TRY(hipMalloc(&idx->d_rows, (size_t)N * W * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&idx->d_sorted, (size_t)N * W * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&idx->d_perm, (size_t)N * sizeof(int32_t)));
     // A is padded so that fixed-size windows around any position stay inside the allocation
     HIP_TRY(hipMalloc(&idx->d_A, (size_t)N + kAdjPad));
     HIP_TRY(hipMemsetAsync(idx->d_A + N, 0, kAdjPad, s));
-    HIP_TRY(hipMalloc(&t.dense, (size_t)N * Wd * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&t.flags, (size_t)(1 + Wd) * sizeof(uint32_t)));
-    HIP_TRY(hipMemsetAsync(t.flags, 0, (size_t)(1 + Wd) * sizeof(uint32_t), s));
-    HIP_TRY(launch_pack(tokens, N, g, (uint32_t)idx->V, dbits, Wd, idx->d_rows, t.dense, t.flags, s));
-    HIP_TRY(launch_varying_bits(t.dense, N, Wd, t.flags + 1, s));
-    std::vector<uint32_t> flags(1 + Wd);
-    HIP_TRY(hipMemcpyAsync(flags.data(), t.flags, flags.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (flags[0]) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);
-
-    // stable LSD radix sort of ids by the dense key: last word first, low digit first
-    HIP_TRY(hipMalloc(&t.counts, radix_counts_words(N) * sizeof(uint32_t)));
-    for (int b = 0; b < 2; ++b) {
-        HIP_TRY(hipMalloc(&t.keys[b], (size_t)N * sizeof(uint32_t)));
-        HIP_TRY(hipMalloc(&t.vals[b], (size_t)N * sizeof(int32_t)));
-    }
-    int cur = 0;
-    HIP_TRY(launch_iota(t.vals[cur], N, s));
-    for (int d = Wd - 1; d >= 0; --d) {
-        const uint32_t vary = flags[1 + d];
-        if (!vary) continue;
-        HIP_TRY(launch_gather_word(t.dense, t.vals[cur], N, Wd, d, t.keys[cur], s));
-        int last_digit = -1;
-        for (int dg = 0; dg < 4; ++dg)
-            if ((vary >> (8 * dg)) & 0xFFu) last_digit = dg;
-        for (int dg = 0; dg < 4; ++dg) {
-            if (!((vary >> (8 * dg)) & 0xFFu)) continue;
-            HIP_TRY(launch_radix_pass(t.keys[cur], t.vals[cur], N, 8 * dg, t.counts, t.keys[cur ^ 1],
-                                      t.vals[cur ^ 1], dg != last_digit, s));
-            cur ^= 1;
-        }
-    }
-    HIP_TRY(hipMemcpyAsync(idx->d_perm, t.vals[cur], (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    lcp_status st = sort_rows(tokens, N, idx->g, idx->V, s, idx->d_rows, idx->d_perm);
+    if (st != LCP_OK) return st;
     HIP_TRY(launch_gather_rows(idx->d_rows, idx->d_perm, N, W, idx->d_sorted, s));
-    HIP_TRY(launch_adjacent_lcp(idx->d_sorted, N, g, idx->d_A, s));
-    idx->stab_levels = search_table_levels(N);
-    if (idx->stab_levels > 0) {
-        HIP_TRY(hipMalloc(&idx->d_stab, (size_t)search_table_entries(idx->stab_levels) * sizeof(uint4)));
-        HIP_TRY(launch_search_tables(idx->d_sorted, N, W, idx->stab_levels, idx->d_stab, s));
+    return finish_index(idx, s);
+}
+
+struct AppendTemps {
+    uint32_t* keys = nullptr;    // new rows, key form, local id order
+    uint32_t* sorted = nullptr;  // new rows, sorted
+    int32_t* perm = nullptr;     // local ids in sorted order
+    int64_t* ub = nullptr;       // old rows <= each sorted new row
+    ~AppendTemps() {
+        if (keys) hipFree(keys);
+        if (sorted) hipFree(sorted);
+        if (perm) hipFree(perm);
+        if (ub) hipFree(ub);
     }
+};
+
+struct NewBuffers {
+    uint32_t* rows = nullptr;
+    uint32_t* sorted = nullptr;
+    int32_t* perm = nullptr;
+    uint8_t* A = nullptr;
+    ~NewBuffers() {
+        if (rows) hipFree(rows);
+        if (sorted) hipFree(sorted);
+        if (perm) hipFree(perm);
+        if (A) hipFree(A);
+    }
+};
+
+// Rows with ids N..N+n-1: the result equals a build over the concatenation.
+lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_t s) {
+    for (auto& kv : idx->ctx) HIP_TRY(hipStreamSynchronize(kv.first));  // no query may still read the index
+    const int64_t N = idx->N;
+    const int W = idx->g.W;
+    AppendTemps t;
+    HIP_TRY(hipMalloc(&t.keys, (size_t)n * W * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&t.sorted, (size_t)n * W * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&t.perm, (size_t)n * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&t.ub, (size_t)n * sizeof(int64_t)));
+    lcp_status st = sort_rows(tokens, n, idx->g, idx->V, s, t.keys, t.perm);
+    if (st != LCP_OK) return st;  // index unchanged
+    HIP_TRY(launch_gather_rows(t.keys, t.perm, n, W, t.sorted, s));
+    HIP_TRY(launch_upper_bounds(idx->d_sorted, N, t.sorted, n, idx->g, t.ub, s));
+    NewBuffers nb;
+    const int64_t M = N + n;
+    HIP_TRY(hipMalloc(&nb.rows, (size_t)M * W * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&nb.sorted, (size_t)M * W * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&nb.perm, (size_t)M * sizeof(int32_t)));
+    HIP_TRY(hipMalloc(&nb.A, (size_t)M + kAdjPad));
+    HIP_TRY(hipMemsetAsync(nb.A + M, 0, kAdjPad, s));
+    HIP_TRY(hipMemcpyAsync(nb.rows, idx->d_rows, (size_t)N * W * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(nb.rows + (size_t)N * W, t.keys, (size_t)n * W * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_merge_sorted(idx->d_sorted, idx->d_perm, N, t.sorted, t.perm, t.ub, n, W, nb.sorted, nb.perm, s));
     HIP_TRY(hipStreamSynchronize(s));
-    return LCP_OK;
+    // swap in the merged arrays; the old ones are freed with the NewBuffers holder
+    std::swap(idx->d_rows, nb.rows);
+    std::swap(idx->d_sorted, nb.sorted);
+    std::swap(idx->d_perm, nb.perm);
+    std::swap(idx->d_A, nb.A);
+    if (idx->d_stab) hipFree(idx->d_stab);
+    idx->d_stab = nullptr;
+    if (idx->d_bmin) hipFree(idx->d_bmin);
+    idx->d_bmin = nullptr;
+    idx->N = M;
+    return finish_index(idx, s);
 }
 
 }  // namespace
@@ -418,6 +506,8 @@ lcp_status lcp_index_build(const void* tokens, int64_t N, int32_t L, int32_t V, 
         delete idx;
         return fail(LCP_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     }
+    if (hipDeviceGetAttribute(&idx->cus, hipDeviceAttributeMultiprocessorCount, idx->device) != hipSuccess)
+        idx->cus = 256;
     idx->N = N;
     idx->L = L;
     idx->V = V;
@@ -453,6 +543,46 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
                              const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
                              void* stream) {
     return query_dev(index, Path::Scan, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_topk_persistent(const lcp_index* idx, const void* queries, const int64_t* q_count_dev,
+                               const int32_t* k_dev, const int64_t* off_dev, int32_t k_max, int32_t* out_ids,
+                               int32_t* out_lcp, int32_t blocks, void* stream) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (!queries || !q_count_dev || !k_dev || !off_dev || !out_ids || !out_lcp)
+        return fail(LCP_EINVAL, "NULL device pointer");
+    if (k_max < 1 || k_max > LCP_K_MAX) return fail(LCP_EINVAL, "k_max = %d is outside [1, %d]", k_max, LCP_K_MAX);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(idx->mu);
+    StreamCtx* c = nullptr;
+    lcp_status st = get_ctx(idx, s, &c);
+    if (st != LCP_OK) return st;
+    if (!c->d_counter) HIP_TRY(hipMalloc(&c->d_counter, sizeof(unsigned long long)));
+    // 6 resident waves per SIMD, 4 SIMDs per CU, 4 waves per block
+    const int b = blocks > 0 ? blocks : idx->cus * 6;
+    QueryBatch qb;
+    qb.raw = queries;
+    qb.Q = 0;  // read on the device
+    qb.k = k_dev;
+    qb.off = off_dev;
+    qb.k_uniform = 0;
+    qb.q_base = 0;
+    qb.k_max = k_max;
+    qb.out_ids = out_ids;
+    qb.out_lcp = out_lcp;
+    HIP_TRY(launch_index_query_persistent(idx->view(), qb, q_count_dev, c->d_counter, b, s));
+    return LCP_OK;
+}
+
+lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, void* stream) {
+    if (!index) return fail(LCP_EINVAL, "index is NULL");
+    if (n == 0) return LCP_OK;
+    if (!tokens) return fail(LCP_EINVAL, "tokens is NULL");
+    if (n < 0 || index->N + n > INT32_MAX)
+        return fail(LCP_EINVAL, "n = %lld would take N past 2^31 - 1", (long long)n);
+    std::lock_guard<std::mutex> lk(index->mu);
+    HIP_TRY(hipSetDevice(index->device));
+    return append_into(index, tokens, n, static_cast<hipStream_t>(stream));
 }
 
 void lcp_index_free(lcp_index* index) { destroy_index(index); }

@@ -322,6 +322,17 @@ int64_t search_table_entries(int levels) {
 // integer arithmetic as the query's search), then store its pivot's first four
 // key words (zero past the row's end).  Entries of nodes the search never
 // reaches are zero.
+// Tie summaries: bmin[b] = the smallest id among sorted positions
+// [64b, min(64b + 64, N)).  One wave per block of positions.
+__global__ void k_block_min(const int32_t* __restrict__ perm, int64_t N, uint32_t* __restrict__ bmin) {
+    const int64_t nb = (N + kWave - 1) / kWave;
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (b >= nb) return;  // whole waves leave together
+    const int64_t j = b * kWave + lane_id();
+    const uint32_t v = wave_min_u32(j < N ? (uint32_t)perm[j] : 0xFFFFFFFFu);
+    if (lane_id() == 0) bmin[b] = v;
+}
+
 __global__ void k_search_tables(const uint32_t* __restrict__ sorted, int64_t N, int W, int levels,
                                 uint4* __restrict__ stab) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -367,7 +378,87 @@ __global__ void k_search_tables(const uint32_t* __restrict__ sorted, int64_t N, 
     stab[t] = key;
 }
 
+// ------------------------------------------------------------ append (merge)
+
+// -1, 0, +1: order of two key-form rows
+__device__ __forceinline__ int compare_rows(const uint32_t* a, const uint32_t* b, int W) {
+    for (int w = 0; w < W; ++w)
+        if (a[w] != b[w]) return a[w] < b[w] ? -1 : 1;
+    return 0;
+}
+
+// One thread per new row: binary search for the number of old rows <= it
+// (old rows equal to a new row come first: they have smaller ids).
+__global__ void k_upper_bounds(const uint32_t* __restrict__ sorted, int64_t N, const uint32_t* __restrict__ newrows,
+                               int64_t n, int W, int64_t* __restrict__ ub) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t* x = newrows + j * W;
+    int64_t lo = 0, hi = N;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (compare_rows(sorted + mid * W, x, W) <= 0)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    ub[j] = lo;
+}
+
+// Old row i moves right by the number of new rows placed before it: those
+// with ub <= i (ub is non-decreasing along the sorted new rows).
+__global__ void k_merge_old(const uint32_t* __restrict__ sorted, const int32_t* __restrict__ perm, int64_t N,
+                            const int64_t* __restrict__ ub, int64_t n, int W, uint32_t* __restrict__ out_sorted,
+                            int32_t* __restrict__ out_perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (ub[mid] <= i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const int64_t dst = i + lo;
+    for (int w = 0; w < W; ++w) out_sorted[dst * W + w] = sorted[i * W + w];
+    out_perm[dst] = perm[i];
+}
+
+__global__ void k_merge_new(const uint32_t* __restrict__ newrows, const int32_t* __restrict__ newperm, int64_t N,
+                            const int64_t* __restrict__ ub, int64_t n, int W, uint32_t* __restrict__ out_sorted,
+                            int32_t* __restrict__ out_perm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t dst = ub[j] + j;
+    for (int w = 0; w < W; ++w) out_sorted[dst * W + w] = newrows[j * W + w];
+    out_perm[dst] = (int32_t)(N + newperm[j]);
+}
+
 // ------------------------------------------------------------ launchers
+
+hipError_t launch_upper_bounds(const uint32_t* sorted, int64_t N, const uint32_t* newrows, int64_t n, RowGeo g,
+                               int64_t* ub, hipStream_t s) {
+    hipLaunchKernelGGL(k_upper_bounds, dim3(blocks_for(n, 256)), dim3(256), 0, s, sorted, N, newrows, n, g.W, ub);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, int64_t N, const uint32_t* newrows,
+                               const int32_t* newperm, const int64_t* ub, int64_t n, int W, uint32_t* out_sorted,
+                               int32_t* out_perm, hipStream_t s) {
+    hipLaunchKernelGGL(k_merge_old, dim3(blocks_for(N, 256)), dim3(256), 0, s, sorted, perm, N, ub, n, W, out_sorted,
+                       out_perm);
+    hipLaunchKernelGGL(k_merge_new, dim3(blocks_for(n, 256)), dim3(256), 0, s, newrows, newperm, N, ub, n, W,
+                       out_sorted, out_perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_min(const int32_t* perm, int64_t N, uint32_t* bmin, hipStream_t s) {
+    const int64_t nb = block_min_entries(N);
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_min, dim3(blocks_for(nb, 4)), dim3(256), 0, s, perm, N, bmin);
+    return hipGetLastError();
+}
 
 hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
                                 hipStream_t s) {

@@ -23,8 +23,19 @@ hipError_t launch_gather_rows(const uint32_t* keys, const int32_t* perm, int64_t
                               hipStream_t s);
 hipError_t launch_adjacent_lcp(const uint32_t* sorted, int64_t N, RowGeo g, uint8_t* A, hipStream_t s);
 
+// ub[j] = number of rows of `sorted` (N rows) that are <= row j of `newrows` (n rows, sorted)
+hipError_t launch_upper_bounds(const uint32_t* sorted, int64_t N, const uint32_t* newrows, int64_t n, RowGeo g,
+                               int64_t* ub, hipStream_t s);
+// merge two sorted row sets (old first on ties); new ids are N + newperm[j]
+hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, int64_t N, const uint32_t* newrows,
+                               const int32_t* newperm, const int64_t* ub, int64_t n, int W, uint32_t* out_sorted,
+                               int32_t* out_perm, hipStream_t s);
 hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
                                 hipStream_t s);
+
+// tie summaries: smallest id of each run of 64 sorted positions
+inline int64_t block_min_entries(int64_t N) { return (N + kWave - 1) / kWave; }
+hipError_t launch_block_min(const int32_t* perm, int64_t N, uint32_t* bmin, hipStream_t s);
 
 // ---- queries
 constexpr int kAdjWindow = 1024;                  // bytes of A one query wave stages in LDS
@@ -45,6 +56,7 @@ struct IndexView {
     const int32_t* perm;     // [N]
     const uint8_t* A;        // [N] adjacent LCP
     const uint4* stab;       // search tables (may be null when levels == 0)
+    const uint32_t* bmin;    // [ceil(N/64)] smallest id of each run of 64 sorted positions
     int stab_levels;
     int64_t N;
     RowGeo g;
@@ -70,6 +82,10 @@ __device__ __forceinline__ int64_t query_off(const QueryBatch& qb, int64_t qi) {
 }
 
 hipError_t launch_index_query(const IndexView& ix, const QueryBatch& qb, hipStream_t s);
+// persistent form: `blocks` blocks of 4 waves; the batch size is read from
+// q_count (device); `counter` (device) is reset by a kernel in the same stream
+hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
+                                         unsigned long long* counter, int blocks, hipStream_t s);
 
 // Full scan.  `part` must hold scan_partial_entries(...) keys.
 struct ScanPlan {

@@ -38,6 +38,7 @@ namespace lcpx {
 constexpr int kQueryWaves = 4;
 constexpr int kTieUnroll = 8;
 constexpr int kFewTied = 16;  // tied selections of at most this many ids use repeated wave minima
+constexpr int kSelMax = kAdjWindow / 4;  // selected blocks the pruned tie scan keeps in the LDS window
 
 // A[j] for the 64 positions j = j0 + dir * lane: from the wave's LDS window
 // when the whole chunk lies inside it, else from global memory.  Lanes whose
@@ -53,20 +54,140 @@ __device__ __forceinline__ int a_lane(const uint8_t* __restrict__ A, const uint8
     return in_win ? (int)win[j - wbase] : (int)A[j];
 }
 
+// The m lowest ids among the tied positions [l, in_lo) and [in_hi, r) using
+// the per-64-position minima bmin (section 6.2's range scan, pruned).
+// Every position lies either in a run of 64 that sits wholly inside one of the
+// two ranges (a full block) or in one of the at most four partial runs at
+// their ends.  Representatives are the full blocks' minima and the partial
+// positions' own ids: all distinct ids of tied rows.  With tau the m-th
+// smallest representative, at least m tied ids are <= tau, so every answer is
+// <= tau; an answer in a full block makes that block's minimum <= tau, and
+// exactly m representatives are <= tau, so at most m full blocks need reading.
+// Phase 0 finds tau from the minima, phase 1 reads the selected blocks (their
+// indices kept in `sel`, the wave's LDS window, <= kSelMax entries) and the
+// partial positions, keeping ids <= tau.
+template <int NR>
+__device__ __forceinline__ void tied_pruned(const IndexView& ix, int64_t l, int64_t in_lo, int64_t in_hi, int64_t r,
+                                         int m, int c, int32_t* __restrict__ oid, int32_t* __restrict__ olc,
+                                         uint32_t* sel) {
+    const int lane = lane_id();
+    const int64_t ss[2] = {l, in_hi};
+    const int64_t ee[2] = {in_lo, r};
+    int64_t hs[2], te[2], bf[2], nbk[2];
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+        const int64_t up = (ss[sg] + kWave - 1) & ~(int64_t)(kWave - 1);
+        const int64_t h = ee[sg] < up ? ee[sg] : up;                        // head run [s, h)
+        const int64_t dn = ee[sg] & ~(int64_t)(kWave - 1);
+        const int64_t t = dn > h ? dn : h;                                  // tail run [t, e)
+        hs[sg] = h;
+        te[sg] = t;
+        bf[sg] = h / kWave;                                                 // full blocks [h/64, t/64)
+        nbk[sg] = t / kWave - h / kWave;
+    }
+    const int64_t nbt = nbk[0] + nbk[1];
+    int nsel = 0;
+    uint32_t tau = 0xFFFFFFFFu;
+    WaveList<NR> lst;
+#pragma unroll 1
+    for (int ph = 0; ph < 2; ++ph) {
+        lst.init();
+        uint32_t px[4];
+        bool pv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sg = u >> 1;
+            const int64_t a = (u & 1) ? te[sg] : ss[sg];
+            const int64_t b = (u & 1) ? ee[sg] : hs[sg];
+            const int64_t j = a + lane;
+            pv[u] = j < b;
+            px[u] = pv[u] ? (uint32_t)ix.perm[j] : 0u;
+        }
+#pragma unroll 1
+        for (int u = 0; u < 4; ++u) {
+            uint32_t x = px[0];
+            bool v = pv[0];
+#pragma unroll
+            for (int uu = 1; uu < 4; ++uu) {
+                x = u == uu ? px[uu] : x;
+                v = u == uu ? pv[uu] : v;
+            }
+            lst.offer((uint64_t)x, v && x <= tau, m);
+        }
+        // items: 64 block minima each (phase 0) or one selected block of 64 ids (phase 1)
+        const int64_t nit = ph == 0 ? (nbt + kWave - 1) / kWave : (int64_t)nsel;
+#pragma unroll 1
+        for (int64_t t0 = 0; t0 < nit; t0 += kTieUnroll) {
+            uint32_t x[kTieUnroll];
+            bool v[kTieUnroll];
+#pragma unroll
+            for (int u = 0; u < kTieUnroll; ++u) {  // all loads in flight before any is used
+                const int64_t t = t0 + u;
+                if (ph == 0) {
+                    const int64_t vb = t * kWave + lane;
+                    v[u] = t < nit && vb < nbt;
+                    const int64_t pb = vb < nbk[0] ? bf[0] + vb : bf[1] + (vb - nbk[0]);
+                    x[u] = v[u] ? ix.bmin[pb] : 0u;
+                } else {
+                    v[u] = t < nit;
+                    const int64_t blk = v[u] ? (int64_t)sel[t] : 0;
+                    x[u] = v[u] ? (uint32_t)ix.perm[blk * kWave + lane] : 0u;
+                }
+            }
+#pragma unroll 1
+            for (int u = 0; u < kTieUnroll && t0 + u < nit; ++u) {
+                uint32_t xx = x[0];
+                bool vv = v[0];
+#pragma unroll
+                for (int uu = 1; uu < kTieUnroll; ++uu) {
+                    xx = u == uu ? x[uu] : xx;
+                    vv = u == uu ? v[uu] : vv;
+                }
+                lst.offer((uint64_t)xx, vv && xx <= tau, m);
+            }
+        }
+        if (ph == 0) {
+            const uint64_t tk = lst.get(m - 1);
+            tau = tk < 0xFFFFFFFFull ? (uint32_t)tk : 0xFFFFFFFFu;
+            nsel = 0;
+            for (int64_t b0 = 0; b0 < nbt; b0 += kWave) {
+                const int64_t vb = b0 + lane;
+                const int64_t pb = vb < nbk[0] ? bf[0] + vb : bf[1] + (vb - nbk[0]);
+                const bool hit = vb < nbt && ix.bmin[pb] <= tau;
+                const uint64_t bal = ballot(hit);
+                const int pos = nsel + count_below(bal);
+                if (hit && pos < kSelMax) sel[pos] = (uint32_t)pb;
+                nsel += popc64(bal);
+            }
+            nsel = nsel < kSelMax ? nsel : kSelMax;  // at most m <= kSelMax by the argument above
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        const int e = rr * kWave + lane;
+        if (e < m) {
+            oid[e] = (int32_t)(uint32_t)lst.v[rr];
+            olc[e] = c;
+        }
+    }
+}
+
 template <int NR, int VEC>
-__device__ __forceinline__ void index_query_body(const IndexView& ix, const QueryBatch& qb) {
+__device__ __forceinline__ void index_query_body(const IndexView& ix, const QueryBatch& qb, int64_t qi) {
     extern __shared__ uint32_t s_dyn[];  // [kQueryWaves][W] query words, then [kQueryWaves][kAdjWindow] A bytes
     const RowGeo g = ix.g;
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t qi = (int64_t)blockIdx.x * kQueryWaves + wv;
-    const bool live = qi < qb.Q;
     uint32_t* q = s_dyn + wv * g.W;
     uint8_t* win = reinterpret_cast<uint8_t*>(s_dyn + kQueryWaves * g.W) + wv * kAdjWindow;
-    if (live)
-        for (int w = lane; w < g.W; w += kWave) q[w] = key_word(qb.raw, qi * g.L, g, w);
-    __syncthreads();
-    if (!live) return;
+    // the wave's own LDS slot: the writes below are seen by its later reads
+    for (int w = lane; w < g.W; w += kWave) q[w] = key_word(qb.raw, qi * g.L, g, w);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     const int64_t N = ix.N;
     const int k = query_k(qb, qi);
@@ -292,6 +413,8 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 oid[n_gt + lane] = (int32_t)mine;
                 olc[n_gt + lane] = c;
             }
+        } else if (m <= kSelMax && (in_lo - l) + (r - in_hi) >= (int64_t)kWave * 4 * (m > 8 ? m : 8)) {
+            tied_pruned<NR>(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else {
             WaveList<NR> tied;
             tied.init();
@@ -335,14 +458,56 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
 // 8,192-query batch is resident at once.  Large lists (k > 256) keep their
 // registers instead.
 template <int NR, int VEC>
+__device__ __forceinline__ void one_query_per_wave(const IndexView& ix, const QueryBatch& qb) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t qi = (int64_t)blockIdx.x * kQueryWaves + wv;
+    if (qi < qb.Q) index_query_body<NR, VEC>(ix, qb, qi);
+}
+
+// Persistent form: a grid that fills the GPU once; each wave takes the next
+// query from a device counter (reset to 0 before the launch) until the batch
+// size read from device memory is reached.  Queries of uneven cost balance
+// themselves; the order in which waves take them never reaches the output.
+template <int NR, int VEC>
+__device__ __forceinline__ void queries_from_counter(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
+                                                     unsigned long long* counter) {
+    const int64_t Q = *q_count;
+#pragma unroll 1
+    for (;;) {
+        unsigned long long got = 0;
+        if (lane_id() == 0) got = atomicAdd(counter, 1ull);
+        const int64_t qi = (int64_t)readlane64(got, 0);
+        if (qi >= Q) break;
+        index_query_body<NR, VEC>(ix, qb, qi);
+    }
+}
+
+template <int NR, int VEC>
 __global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_index_query(
     IndexView ix, QueryBatch qb) {
-    index_query_body<NR, VEC>(ix, qb);
+    one_query_per_wave<NR, VEC>(ix, qb);
 }
 
 template <int VEC>
 __global__ __launch_bounds__(kQueryWaves * kWave) void k_index_query_wide(IndexView ix, QueryBatch qb) {
-    index_query_body<16, VEC>(ix, qb);
+    one_query_per_wave<16, VEC>(ix, qb);
+}
+
+template <int NR, int VEC>
+__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_index_query_persistent(
+    IndexView ix, QueryBatch qb, const int64_t* q_count, unsigned long long* counter) {
+    queries_from_counter<NR, VEC>(ix, qb, q_count, counter);
+}
+
+template <int VEC>
+__global__ __launch_bounds__(kQueryWaves * kWave) void k_index_query_persistent_wide(IndexView ix, QueryBatch qb,
+                                                                                    const int64_t* q_count,
+                                                                                    unsigned long long* counter) {
+    queries_from_counter<16, VEC>(ix, qb, q_count, counter);
+}
+
+__global__ void k_reset_counter(unsigned long long* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
 }
 
 template <int NR>
@@ -366,6 +531,38 @@ static hipError_t launch_nr(const IndexView& ix, const QueryBatch& qb, hipStream
             hipLaunchKernelGGL((k_index_query<NR, 1>), dim3(grid), blk, shm, s, ix, qb);
     }
     return hipGetLastError();
+}
+
+template <int NR>
+static hipError_t launch_persistent_nr(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
+                                       unsigned long long* counter, int blocks, hipStream_t s) {
+    const size_t shm = (size_t)kQueryWaves * (ix.g.W * sizeof(uint32_t) + kAdjWindow);
+    const dim3 blk(kQueryWaves * kWave);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    if constexpr (NR == 16) {
+        if (ix.g.W % 4 == 0)
+            hipLaunchKernelGGL((k_index_query_persistent_wide<4>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+        else if (ix.g.W % 2 == 0)
+            hipLaunchKernelGGL((k_index_query_persistent_wide<2>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+        else
+            hipLaunchKernelGGL((k_index_query_persistent_wide<1>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+    } else {
+        if (ix.g.W % 4 == 0)
+            hipLaunchKernelGGL((k_index_query_persistent<NR, 4>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+        else if (ix.g.W % 2 == 0)
+            hipLaunchKernelGGL((k_index_query_persistent<NR, 2>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+        else
+            hipLaunchKernelGGL((k_index_query_persistent<NR, 1>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
+                                         unsigned long long* counter, int blocks, hipStream_t s) {
+    if (qb.k_max <= 64) return launch_persistent_nr<1>(ix, qb, q_count, counter, blocks, s);
+    if (qb.k_max <= 128) return launch_persistent_nr<2>(ix, qb, q_count, counter, blocks, s);
+    if (qb.k_max <= 256) return launch_persistent_nr<4>(ix, qb, q_count, counter, blocks, s);
+    return launch_persistent_nr<16>(ix, qb, q_count, counter, blocks, s);
 }
 
 hipError_t launch_index_query(const IndexView& ix, const QueryBatch& qb, hipStream_t s) {

@@ -65,6 +65,8 @@ struct ScanQueryState {  // per (wave, query), in LDS
     uint64_t list[NR * kWave];
     uint64_t lim;
     uint64_t msk, qm;
+    int32_t kk;  // min(k, N)
+    int32_t pad_;
 };
 
 // Query key words, computed once per launch for every block to copy.
@@ -97,6 +99,8 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         st_all[idx].lim = kKeyMax;
         st_all[idx].msk = 0;
         st_all[idx].qm = real ? 0 : 1;
+        const int ki = real ? query_k(qb, qblock + idx) : 1;
+        st_all[idx].kk = (int)((int64_t)ki < ix.N ? (int64_t)ki : ix.N);
     }
     for (int idx = threadIdx.x; idx < kScanWaves * TQ * NR * kWave; idx += kScanWaves * kWave)
         st_all[idx / (NR * kWave)].list[idx % (NR * kWave)] = kKeyMax;
@@ -209,8 +213,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                 else
                     lc = W > 2 ? lcp_tail(ix.rows + id * W, q, g, 2) : g.L;
             }
-            const int ki = query_k(qb, q0i + i);
-            const int kk = (int)((int64_t)ki < N ? (int64_t)ki : N);
+            const int kk = st[i].kk;
             const uint64_t lim = st[i].lim;
             const uint64_t key = rank_key(lc, (uint32_t)id);
             WaveList<NR> lst;
@@ -237,8 +240,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
 
 #pragma unroll 1
     for (int i = 0; i < ntq; ++i) {
-        const int ki = query_k(qb, q0i + i);
-        const int kk = (int)((int64_t)ki < N ? (int64_t)ki : N);
+        const int kk = st[i].kk;
         uint64_t* dst = part + ((q0i + i) * nparts + part0 + blockIdx.x) * (int64_t)qb.k_max;
         for (int e = lane; e < qb.k_max; e += kWave) dst[e] = e < kk ? st[i].list[e] : kKeyMax;
     }
@@ -261,11 +263,22 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
     const uint64_t* src = part + (qi * nparts + part_lo) * (int64_t)qb.k_max;
     WaveList<NR> lst;
     lst.init();
-    for (int64_t b = 0; b < total; b += kWave) {
-        const int64_t t = b + lane;
-        const bool act = t < total && (int)(t % qb.k_max) < m;
-        const uint64_t key = act ? src[t] : kKeyMax;
-        lst.offer(key, act && key != kKeyMax, m);
+    constexpr int kMergeUnroll = 8;
+    for (int64_t b = 0; b < total; b += kMergeUnroll * kWave) {
+        uint64_t key[kMergeUnroll];
+#pragma unroll
+        for (int u = 0; u < kMergeUnroll; ++u) {  // all loads in flight before any is used
+            const int64_t t = b + u * kWave + lane;
+            const bool act = t < total && (int)(t % qb.k_max) < m;
+            key[u] = act ? src[t] : kKeyMax;
+        }
+#pragma unroll 1
+        for (int u = 0; u < kMergeUnroll && b + u * kWave < total; ++u) {  // one copy of the offer code
+            uint64_t x = key[0];
+#pragma unroll
+            for (int uu = 1; uu < kMergeUnroll; ++uu) x = u == uu ? key[uu] : x;
+            lst.offer(x, x != kKeyMax, m);
+        }
     }
     if (limit) {
         const uint64_t kth = lst.get(m - 1);
@@ -306,7 +319,8 @@ static int tq_for(int nr, int64_t Q) {
 // The first rows are scanned first, in seed chunks whose merged k-th key
 // becomes every query's starting limit for the remaining chunks.
 constexpr int64_t kChunkMinRows = 2048;
-constexpr int64_t kSeedRowsMax = 65536;
+constexpr int64_t kSeedChunkRows = kScanUnroll * kWave;  // one step per seed chunk
+constexpr int64_t kSeedRowsMax = 32768;
 
 ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     ScanPlan p;
@@ -316,13 +330,12 @@ ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     p.qgroups = (int)((Q + per_group - 1) / per_group);
     const int64_t bytes_per_chunk = Q * (int64_t)k_max * 8;
     const int64_t max_by_mem = bytes_per_chunk > 0 ? ((int64_t)256 << 20) / bytes_per_chunk : 1;
-    // seed: up to 1/8 of the rows (at most kSeedRowsMax) in chunks of kChunkMinRows
+    // seed: up to 1/8 of the rows (at most kSeedRowsMax) in one-step chunks
     p.seed_rows = N / 8 < kSeedRowsMax ? N / 8 : kSeedRowsMax;
-    p.seed_rows = p.seed_rows / kChunkMinRows * kChunkMinRows;
-    p.seed_chunks = (int)(p.seed_rows / kChunkMinRows);
+    p.seed_chunks = (int)(p.seed_rows / kSeedChunkRows);
     if (p.seed_chunks > max_by_mem / 2) p.seed_chunks = (int)(max_by_mem / 2);
-    if (p.seed_chunks < 2) p.seed_chunks = 0;  // too few rows to be worth a seed
-    p.seed_rows = p.seed_chunks * kChunkMinRows;
+    if (p.seed_chunks < 4) p.seed_chunks = 0;  // too few rows to be worth a seed
+    p.seed_rows = p.seed_chunks * kSeedChunkRows;
     const int64_t rest = N - p.seed_rows;
     // main: aim for >= 4096 blocks (16 per CU), chunks of >= kChunkMinRows rows, partials <= 256 MiB
     int64_t chunks = (4096 + p.qgroups - 1) / p.qgroups;
@@ -355,7 +368,7 @@ static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanP
     const dim3 blk(kScanWaves * kWave);
     if (p.seed_chunks > 0) {
         hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)p.seed_chunks, (unsigned)p.qgroups), blk, shm, s, ix, qb,
-                           qkeys, (int64_t)0, p.seed_rows, kChunkMinRows, 0, p.nparts, part, gthr);
+                           qkeys, (int64_t)0, p.seed_rows, kSeedChunkRows, 0, p.nparts, part, gthr);
         hipLaunchKernelGGL((k_scan_merge<NR>), dim3((unsigned)((qb.Q + kScanWaves - 1) / kScanWaves)), blk, 0, s, qb,
                            ix.N, p.nparts, 0, p.seed_chunks, part, gthr);
     }

@@ -305,3 +305,68 @@ def run_synchronous(index, requests: List[Request], scan: bool = True, max_wall_
     rep["mode"] = "synchronous, one request per call"
     rep["completed_fraction"] = round(len(done) / max(len(requests), 1), 4)
     return rep
+
+
+def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0, append=None,
+                    max_wall_s: float = 120.0) -> dict:
+    """Paced stream of query batches (the GNC loop of section 7, Table "GNC
+    benchmark": each step queries the current readings of every sensor).
+
+    steps        : iterable of [S, L] token arrays, one batch per step
+    rate_hz      : target step rate; step t is released at t / rate_hz
+    append_every : every that many steps, `append(index, batch)` is called with
+                   the step's batch and must return the index to use next
+                   (rows join the database with the next ids)
+    Returns the achieved step rate and step latency percentiles (latency =
+    completion - release time, so a late step also delays the next ones).
+    """
+    import torch
+    dev = index.device
+    lat = []
+    appends_ms = []
+    buf = {}
+    t0 = time.perf_counter()
+    n = 0
+    for t, batch in enumerate(steps):
+        release = t / rate_hz
+        while time.perf_counter() - t0 < release:
+            pass
+        raw = np.ascontiguousarray(batch if batch.dtype != np.uint16 else batch.view(np.int16))
+        if buf.get("shape") != raw.shape:  # pinned staging and outputs, reused across steps
+            qdt = torch.uint8 if raw.dtype == np.uint8 else torch.int16
+            buf = {"shape": raw.shape,
+                   "qh": torch.empty(raw.shape, dtype=qdt, pin_memory=True),
+                   "qd": torch.empty(raw.shape, dtype=qdt, device=dev),
+                   "ids": torch.empty(raw.shape[0] * k, dtype=torch.int32, device=dev),
+                   "lcp": torch.empty(raw.shape[0] * k, dtype=torch.int32, device=dev),
+                   "ids_h": torch.empty(raw.shape[0] * k, dtype=torch.int32, pin_memory=True),
+                   "lcp_h": torch.empty(raw.shape[0] * k, dtype=torch.int32, pin_memory=True)}
+        buf["qh"].numpy()[:] = raw
+        buf["qd"].copy_(buf["qh"], non_blocking=True)
+        index.topk(buf["qd"], k, out=(buf["ids"], buf["lcp"]))
+        buf["ids_h"].copy_(buf["ids"], non_blocking=True)
+        buf["lcp_h"].copy_(buf["lcp"], non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        done = time.perf_counter() - t0
+        lat.append((done - release) * 1e3)
+        n += 1
+        if append_every and append is not None and (t + 1) % append_every == 0:
+            a0 = time.perf_counter()
+            index = append(index, batch)
+            torch.cuda.synchronize()
+            appends_ms.append((time.perf_counter() - a0) * 1e3)
+        if done > max_wall_s:
+            break
+    wall = time.perf_counter() - t0
+    lat = np.asarray(lat)
+    return {
+        "steps": n,
+        "target_hz": rate_hz,
+        "achieved_hz": round(n / wall, 1),
+        "p50_step_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_step_ms": round(float(np.percentile(lat, 99)), 4),
+        "max_step_ms": round(float(lat.max()), 4),
+        "appends": len(appends_ms),
+        "append_ms_mean": round(float(np.mean(appends_ms)), 3) if appends_ms else None,
+        "index": index,
+    }

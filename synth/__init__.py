@@ -36,6 +36,8 @@ __all__ = [
     "c5_sensor",
     "random_rows",
     "sha256_of",
+    "uneven_k",
+    "long_ties",
 ]
 
 
@@ -269,3 +271,39 @@ def random_rows(rng: np.random.Generator, n: int, L: int, V: int, dtype=None) ->
     """Uniform tokens in [0, V)."""
     dt = dtype or _dtype_for(V)
     return rng.integers(0, V, size=(n, L), dtype=np.int64).astype(dt)
+
+
+def uneven_k(Q: int, seed: int = 1013, choices=(1, 10, 100)) -> np.ndarray:
+    """Per-query k drawn uniformly from `choices` (the uneven-batch workload)."""
+    rng = np.random.default_rng(seed)
+    return np.asarray(choices, dtype=np.int32)[rng.integers(0, len(choices), Q)]
+
+
+def long_ties(seed: int = 1021, N: int = 400_000, L: int = 8, Q: int = 512,
+              probs=(0.80, 0.15, 0.002, 0.048), k_choices=(1, 10, 54, 100, 250)) -> Workload:
+    """Heavily duplicated rows, so that the rows tied at the cutoff LCP number
+    in the thousands to hundreds of thousands.
+
+    Every db token is i.i.d. over V=4 symbols with probabilities `probs`
+    (symbol 0 dominant).  Queries, in this order: Q/8 all-zero rows; Q/8 rows
+    0^(L-1) 2 (few exact matches, with the rows of last token 3 sorted after
+    them and those of tokens 0 and 1 before, so rows tied one level up sit on
+    both sides of them); Q/4 rows 0^j x
+    then zeros, j uniform in [0, L), x uniform in {1, 2, 3}; Q/4 copies of
+    random db rows; the rest fresh draws from the db distribution.  k uniform
+    on `k_choices`.
+    """
+    r_db, r_q, r_k, _ = _streams(seed)
+    db = r_db.choice(4, size=(N, L), p=np.asarray(probs)).astype(np.uint8)
+    n8, n4 = Q // 8, Q // 4
+    zeros = np.zeros((n8, L), dtype=np.uint8)
+    both = np.zeros((n8, L), dtype=np.uint8)
+    both[:, L - 1] = 2
+    step = np.zeros((n4, L), dtype=np.uint8)
+    j = r_q.integers(0, L, n4)
+    step[np.arange(n4), j] = r_q.integers(1, 4, n4)
+    copies = db[r_q.choice(N, size=n4, replace=False)]
+    fresh = r_q.choice(4, size=(Q - 2 * n8 - 2 * n4, L), p=np.asarray(probs)).astype(np.uint8)
+    queries = np.ascontiguousarray(np.concatenate([zeros, both, step, copies, fresh], axis=0))
+    kk = np.asarray(k_choices, dtype=np.int32)[r_k.integers(0, len(k_choices), Q)]
+    return Workload("long_ties", np.ascontiguousarray(db), queries, kk, 4)

@@ -246,6 +246,45 @@ def test_groups_far_beyond_the_staged_window(P):
     check_against_oracle(P, db, qs, ks, 4, "skewed long groups")
 
 
+def _tie_shape(db, q, k):
+    """(c, rows above c, tied rows at c) for one query, from the oracle's LCPs."""
+    lc = O.lcp_against(db, q)
+    G = np.cumsum(np.bincount(lc, minlength=db.shape[1] + 2)[::-1])[::-1]  # G[d] = rows with LCP >= d
+    kp = min(int(k), db.shape[0])
+    c = max(d for d in range(db.shape[1] + 1) if G[d] >= kp)
+    return c, int(G[c + 1]), int(G[c] - G[c + 1])
+
+
+def test_long_tied_blocks(P):
+    """Rows tied at the cutoff number in the thousands to hundreds of
+    thousands (V=4, one dominant symbol): the index kernel prunes them with the
+    per-64-position id minima.  Both paths and the persistent launch against
+    the oracle; the workload must reach the pruned selection (m <= 256 and at
+    least 256*max(m, 8) tied rows), also with rows above the cutoff."""
+    import torch
+    w = synth.long_ties()
+    pruned = with_inner = 0
+    for qi in range(w.Q):
+        c, n_gt, tn = _tie_shape(w.db, w.queries[qi], w.k[qi])
+        m = min(int(w.k[qi]), w.N) - n_gt
+        if c >= 1 and m <= 256 and tn >= 256 * max(m, 8):
+            pruned += 1
+            with_inner += n_gt > 0
+    assert pruned >= 100 and with_inner >= 5, (pruned, with_inner)
+    check_against_oracle(P, w.db, w.queries, w.k, w.V, "long tied blocks")
+    qd = P.to_device_tokens(w.queries)
+    with P.Index(w.db, w.V) as idx:
+        ref = idx.topk(qd, w.k)
+        kd = torch.from_numpy(w.k).cuda()
+        od = torch.from_numpy(ref.offsets).cuda()
+        cnt = torch.tensor([w.Q], dtype=torch.int64, device="cuda")
+        ids = torch.full_like(ref.ids, -9)
+        lcps = torch.full_like(ref.lcps, -9)
+        idx.topk_persistent(qd, cnt, kd, od, int(w.k.max()), ids, lcps)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps)
+
+
 def test_served_results_equal_alone(P):
     """Continuous batching on the GPU: every request's answer equals the
     oracle's answer for that request alone."""
@@ -259,3 +298,134 @@ def test_served_results_equal_alone(P):
     for r in reqs[:: max(1, len(reqs) // 60)]:
         wi, wl, _ = oracle.c_topk(w.db, r.queries, r.k)
         assert (r.ids.reshape(-1) == wi).all() and (r.lcps.reshape(-1) == wl).all(), r.rid
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_append_equals_build_over_concatenation(P, seed):
+    """Appending rows (ids N, N+1, ...) yields the index a build over the
+    concatenated rows would give: same order, adjacent LCP, id-order rows and
+    answers; equal rows across batches keep ascending ids."""
+    import torch
+    rng = np.random.default_rng(300 + seed)
+    L, V = [(6, 4), (24, 16), (9, 300)][seed]
+    a = synth.random_rows(rng, 3000, L, V)
+    b = np.concatenate([synth.random_rows(rng, 500, L, V), a[:50]])      # duplicates of old rows
+    c = np.concatenate([b[10:20], synth.random_rows(rng, 37, L, V)])     # duplicates of appended rows
+    whole = np.concatenate([a, b, c])
+    qs = np.concatenate([synth.random_rows(rng, 40, L, V), whole[rng.integers(0, len(whole), 24)]])
+    ks = rng.integers(1, 80, qs.shape[0]).astype(np.int32)
+    with P.Index(a, V) as idx:
+        idx.append(b)
+        idx.append(c)
+        assert idx.N == len(whole)
+        va = {k: v.cpu().numpy() for k, v in idx.views().items()}
+        ra = idx.topk(qs, ks)
+        torch.cuda.synchronize()
+        got = (ra.ids.cpu().numpy(), ra.lcps.cpu().numpy())
+    with P.Index(whole, V) as ref:
+        vb = {k: v.cpu().numpy() for k, v in ref.views().items()}
+    for key in ("perm", "adj_lcp", "sorted_keys", "id_keys"):
+        assert (va[key] == vb[key]).all(), key
+    want = O.sorted_permutation(whole)
+    assert (va["perm"] == want).all()
+    wi, wl, _ = oracle.c_topk(whole, qs, ks)
+    assert (got[0] == wi).all() and (got[1] == wl).all()
+
+
+def test_append_rejects_out_of_range_and_keeps_index(P):
+    import torch
+    db = np.zeros((100, 4), np.uint8)
+    with P.Index(db, 5) as idx:
+        with pytest.raises(P.LcpError) as e:
+            idx.append(np.full((3, 4), 9, np.uint8))
+        assert e.value.status == -4 and idx.N == 100
+        idx.append(np.ones((2, 4), np.uint8))
+        r = idx.topk(np.ones((1, 4), np.uint8), 3)
+        torch.cuda.synchronize()
+        assert r.ids.cpu().tolist() == [100, 101, 0] and r.lcps.cpu().tolist() == [4, 4, 0]
+
+
+def test_sensor_stream_with_appends(P):
+    """The paced step loop: every step's answers equal the oracle's over the
+    rows appended so far (including the steps right after each append)."""
+    from paper_2602_04936_amd import serve
+    st = synth.SensorStream(seed=77, sensors=200)
+    hist = np.concatenate(list(st.steps(50)), axis=0)
+    steps = list(st.steps(60))
+    db = [hist]
+    seen = []
+
+    def append(index, batch):
+        db.append(batch)
+        index.append(batch)
+        return index
+
+    idx = P.Index(hist, 16)
+    captured = []
+    orig_topk = idx.topk
+
+    def topk_and_keep(q, k, out=None, stream=None):
+        r = orig_topk(q, k, out=out, stream=stream)
+        captured.append((np.concatenate(db, axis=0).shape[0], r.ids[: q.shape[0] * k].cpu().numpy().copy(),
+                         r.lcps[: q.shape[0] * k].cpu().numpy().copy()))
+        return r
+
+    idx.topk = topk_and_keep
+    rep = serve.run_step_stream(idx, iter(steps), rate_hz=2000.0, k=5, append_every=20, append=append)
+    rep.pop("index").close()
+    assert rep["steps"] == 60 and rep["appends"] == 3
+    whole = np.concatenate(db, axis=0)
+    for t, (n_rows, ids, lcps) in enumerate(captured):
+        wi, wl, _ = oracle.c_topk(whole[:n_rows], steps[t], 5)
+        assert (ids == wi).all() and (lcps == wl).all(), t
+
+
+def test_captured_persistent_launch_replays(P):
+    """One persistent launch captured in a HIP graph, replayed for batches of
+    different sizes and uneven k, with eager work and syncs in between: every
+    replay equals the eager index path (and the oracle on a sample)."""
+    import torch
+    from paper_2602_04936_amd import batching
+    w = synth.c3_like(300_000, 3000, seed=12)
+    qd = P.to_device_tokens(w.queries)
+    with P.Index(w.db, w.V) as idx:
+        ref = idx.topk(qd, w.k)
+        torch.cuda.synchronize()
+        ref_ids, ref_lcp = ref.ids.cpu().numpy(), ref.lcps.cpu().numpy()
+        cl = batching.CapturedLaunch(idx, cap_queries=3000, k_max=100)
+        for n in (3000, 1000, 1, 0, 2999, 3000):
+            ids, lcps, off = cl.run(qd[:n], w.k[:n])
+            torch.cuda.synchronize()
+            gi, gl = ids.cpu().numpy(), lcps.cpu().numpy()
+            assert gi.shape[0] == int(w.k[:n].sum())
+            assert (gi == ref_ids[: gi.shape[0]]).all() and (gl == ref_lcp[: gl.shape[0]]).all(), n
+            idx.topk(qd[:7], 3)  # eager work between replays
+            torch.cuda.synchronize()
+        sample = np.arange(0, 3000, 97)
+        wi, wl, woff = oracle.c_topk(w.db, w.queries[sample], w.k[sample])
+        for j, qi in enumerate(sample):
+            a, b = ref.offsets[qi], ref.offsets[qi + 1]
+            assert (ref_ids[a:b] == wi[woff[j]:woff[j + 1]]).all()
+
+
+def test_autotuned_shapes_agree(P):
+    import torch
+    from paper_2602_04936_amd import batching
+    w = synth.c3_like(200_000, 1500, seed=13)
+    qd = P.to_device_tokens(w.queries)
+    with P.Index(w.db, w.V) as idx:
+        res = batching.tune_launch(idx, qd, w.k, reps=2)
+        assert res["best"].ms == min(s.ms for s in res["tried"])
+        ref = idx.topk(qd, w.k)
+        kd = torch.from_numpy(w.k).cuda()
+        od = torch.from_numpy(ref.offsets).cuda()
+        cnt = torch.tensor([w.Q], dtype=torch.int64, device="cuda")
+        for shape in res["tried"]:
+            ids = torch.full_like(ref.ids, -9)
+            lcps = torch.full_like(ref.lcps, -9)
+            if shape.mode == "plain":
+                idx.topk_dev(qd, kd, od, 100, ids, lcps)
+            else:
+                idx.topk_persistent(qd, cnt, kd, od, 100, ids, lcps, blocks=shape.blocks)
+            torch.cuda.synchronize()
+            assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps), shape
