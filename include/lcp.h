@@ -61,6 +61,13 @@ typedef enum {
 /*
  * Build an index over N rows (section 5.2, the sorted-order equivalent of
  * Algorithms 1-2: leaf order of the trie with posting lists in id order).
+ * Besides the sorted rows, their ids and the adjacent-LCP array the index
+ * keeps the top levels of a 65-ary search tree over the sorted rows, for
+ * every run of 64 sorted positions the smallest id in it (used to skip most
+ * of a long run of rows tied at the cutoff LCP), and the first 8 bytes of
+ * every row in id order (the stream the full scan reads).  Device memory:
+ * about N * (8 * row_words + 13.06) bytes plus at most 4.4 MB of search
+ * tables.
  *
  *   tokens : device, [N][L] uint8 (V <= 256) or uint16 (V > 256).  The
  *            index copies them; the caller may free `tokens` after return.
@@ -189,8 +196,9 @@ lcp_status lcp_index_views(const lcp_index* index, const int32_t** perm, const u
 /*
  * How lcp_scan_topk would split a batch of Q queries with largest k = k_max:
  *   query_groups : passes over the database (each group streams all rows once)
- *   chunks       : row chunks per pass after the seed rows
- *   seed_rows    : rows scanned first to give every query a starting limit
+ *   chunks       : row chunks per pass
+ *   seed_rows    : leading rows whose LCP histogram gives every query a
+ *                  starting limit before the pass
  * Any output pointer may be NULL.
  */
 lcp_status lcp_scan_info(const lcp_index* index, int64_t Q, int32_t k_max, int32_t* query_groups,
@@ -201,7 +209,9 @@ lcp_status lcp_scan_info(const lcp_index* index, int64_t Q, int32_t k_max, int32
  * events on its stream around its main kernel (the fused index-path kernel or
  * the scan kernel).  lcp_kernel_time synchronises those events and returns
  * the summed milliseconds and launch count since the last reset.
- *   which : 0 = index-path kernel, 1 = scan kernel, 2 = scan merge kernel.
+ *   which : 0 = index-path kernel, 1 = the scan's main kernel (one pass of
+ *           the rows per query group; not the seed-limit kernels before it),
+ *           2 = scan merge kernel.
  */
 lcp_status lcp_set_kernel_timing(const lcp_index* index, int32_t enable);
 lcp_status lcp_kernel_time(const lcp_index* index, int32_t which, double* total_ms, int64_t* launches);

@@ -80,6 +80,7 @@ struct lcp_index {
     uint4* d_stab = nullptr;
     int stab_levels = 0;
     uint32_t* d_bmin = nullptr;
+    uint2* d_plane = nullptr;
 
     mutable std::mutex mu;
     mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
@@ -98,6 +99,7 @@ struct lcp_index {
         v.stab = d_stab;
         v.stab_levels = stab_levels;
         v.bmin = d_bmin;
+        v.plane = d_plane;
         v.N = N;
         v.g = g;
         return v;
@@ -256,7 +258,7 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
             }
         } else {
             const ScanPlan plan = plan_scan(idx->N, qb.Q, k_max);
-            lcp_status st = ensure_part(c, scan_partial_entries(plan, qb.Q, k_max, idx->g.W));
+            lcp_status st = ensure_part(c, scan_partial_entries(plan, qb.Q, k_max, idx->g));
             if (st != LCP_OK) return st;
             HIP_TRY(launch_scan(ix, qb, plan, c->d_part, s, ev[0], ev[1], ev[2]));
             if (ev[0] && ev[1] && ev[2]) {
@@ -346,6 +348,7 @@ void destroy_index(lcp_index* idx) {
     if (idx->d_A) hipFree(idx->d_A);
     if (idx->d_stab) hipFree(idx->d_stab);
     if (idx->d_bmin) hipFree(idx->d_bmin);
+    if (idx->d_plane) hipFree(idx->d_plane);
     delete idx;
 }
 
@@ -405,6 +408,8 @@ lcp_status finish_index(lcp_index* idx, hipStream_t s) {
     }
     HIP_TRY(hipMalloc(&idx->d_bmin, (size_t)block_min_entries(N) * sizeof(uint32_t)));
     HIP_TRY(launch_block_min(idx->d_perm, N, idx->d_bmin, s));
+    HIP_TRY(hipMalloc(&idx->d_plane, (size_t)N * sizeof(uint2)));
+    HIP_TRY(launch_prefix_plane(idx->d_rows, N, idx->g.W, idx->d_plane, s));
     HIP_TRY(hipStreamSynchronize(s));
     return LCP_OK;
 }
@@ -485,6 +490,8 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
     idx->d_stab = nullptr;
     if (idx->d_bmin) hipFree(idx->d_bmin);
     idx->d_bmin = nullptr;
+    if (idx->d_plane) hipFree(idx->d_plane);
+    idx->d_plane = nullptr;
     idx->N = M;
     return finish_index(idx, s);
 }

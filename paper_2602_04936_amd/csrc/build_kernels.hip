@@ -322,6 +322,14 @@ int64_t search_table_entries(int levels) {
 // integer arithmetic as the query's search), then store its pivot's first four
 // key words (zero past the row's end).  Entries of nodes the search never
 // reaches are zero.
+// Scan prefix plane: the first two key words of every row, id order, so the
+// full scan streams 8 bytes per row instead of the whole row.
+__global__ void k_prefix_plane(const uint32_t* __restrict__ rows, int64_t N, int W, uint2* __restrict__ plane) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    plane[i] = make_uint2(rows[i * W], W > 1 ? rows[i * W + 1] : 0u);
+}
+
 // Tie summaries: bmin[b] = the smallest id among sorted positions
 // [64b, min(64b + 64, N)).  One wave per block of positions.
 __global__ void k_block_min(const int32_t* __restrict__ perm, int64_t N, uint32_t* __restrict__ bmin) {
@@ -450,6 +458,11 @@ hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, int6
                        out_perm);
     hipLaunchKernelGGL(k_merge_new, dim3(blocks_for(n, 256)), dim3(256), 0, s, newrows, newperm, N, ub, n, W,
                        out_sorted, out_perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_plane(const uint32_t* rows, int64_t N, int W, uint2* plane, hipStream_t s) {
+    hipLaunchKernelGGL(k_prefix_plane, dim3(blocks_for(N, 256)), dim3(256), 0, s, rows, N, W, plane);
     return hipGetLastError();
 }
 

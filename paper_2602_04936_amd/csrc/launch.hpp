@@ -33,6 +33,9 @@ hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, int6
 hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
                                 hipStream_t s);
 
+// scan prefix plane: key words 0 and 1 of each row, id order
+hipError_t launch_prefix_plane(const uint32_t* rows, int64_t N, int W, uint2* plane, hipStream_t s);
+
 // tie summaries: smallest id of each run of 64 sorted positions
 inline int64_t block_min_entries(int64_t N) { return (N + kWave - 1) / kWave; }
 hipError_t launch_block_min(const int32_t* perm, int64_t N, uint32_t* bmin, hipStream_t s);
@@ -57,6 +60,7 @@ struct IndexView {
     const uint8_t* A;        // [N] adjacent LCP
     const uint4* stab;       // search tables (may be null when levels == 0)
     const uint32_t* bmin;    // [ceil(N/64)] smallest id of each run of 64 sorted positions
+    const uint2* plane;      // [N] key words 0 and 1 of each row, id order (the scan's stream)
     int stab_levels;
     int64_t N;
     RowGeo g;
@@ -91,16 +95,31 @@ hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& 
 struct ScanPlan {
     int tq;             // queries per wave
     int nr;             // list registers (capacity 64*nr >= k_max)
-    int chunks;         // row chunks after the seed rows (grid x)
+    int chunks;         // row chunks over [seed_rows, N)
     int qgroups;        // query groups (grid y), 4*tq queries each
-    int nparts;         // partial lists per query (seed chunks + chunks)
-    int seed_chunks;    // chunks of rows [0, seed_rows) scanned first to seed the limits
-    int64_t seed_rows;
+    int nparts;         // partial lists per query: seed_chunks + chunks (grid x)
+    int seed_chunks;    // one-step chunks over the sampled rows (first in grid x)
+    int64_t seed_rows;  // rows [0, seed_rows) whose LCP histogram sets each query's starting limit
+    int seed_parts;     // histogram blocks per query
+    int64_t seed_chunk_rows;
     int64_t chunk_rows;
 };
 ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max);
-size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, int W);  // in 8-byte units
-hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* part, hipStream_t s,
+
+// Per-call scratch of the scan, carved from one device allocation.
+struct ScanScratch {
+    int64_t cap;       // partial-list entries per query (nparts * k_max)
+    uint64_t* part;    // [Q][cap]
+    uint64_t* gthr;    // [Q] shared limits
+    uint32_t* cnt;     // [Q] partial entries appended
+    uint32_t* hist;    // [Q][L+1] seed LCP histogram
+    uint32_t* qkeys;   // [Q][W] query key words
+    size_t words;      // total size in 32-bit words
+};
+ScanScratch scan_scratch(const ScanPlan& p, int64_t Q, int32_t k_max, const RowGeo& g, uint64_t* base);
+size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, const RowGeo& g);  // in 8-byte units
+// ev_scan0/ev_scan1 bracket the main scan kernel, ev_merge1 follows the merge
+hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* scratch, hipStream_t s,
                        hipEvent_t ev_scan0, hipEvent_t ev_scan1, hipEvent_t ev_merge1);
 
 }  // namespace lcpx

@@ -183,6 +183,10 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     uint32_t* q = s_dyn + wv * g.W;
     uint8_t* win = reinterpret_cast<uint8_t*>(s_dyn + kQueryWaves * g.W) + wv * kAdjWindow;
+    // the root node of the search tables does not depend on q: its load is
+    // issued before the query's and overlaps it
+    uint4 root = make_uint4(0u, 0u, 0u, 0u);
+    if (ix.stab_levels > 0) root = ix.stab[lane];
     // the wave's own LDS slot: the writes below are seen by its later reads
     for (int w = lane; w < g.W; w += kWave) q[w] = key_word(qb.raw, qi * g.L, g, w);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -231,7 +235,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
         bool less;
         if (depth < ix.stab_levels) {
             // pivot's first four key words from the table (one coalesced load)
-            const uint4 e = ix.stab[level_start + node * kWave + lane];
+            const uint4 e = depth == 0 ? root : ix.stab[level_start + node * kWave + lane];
             const uint64_t ka = ((uint64_t)e.x << 32) | e.y;
             const uint64_t kb = ((uint64_t)e.z << 32) | e.w;
             if (ka != qa) {

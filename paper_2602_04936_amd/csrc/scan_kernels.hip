@@ -10,8 +10,11 @@
 // more than the k-th entry's LCP t: the hot loop tests the first t + 1 tokens
 // of the row's first key word with one AND and one compare against a
 // pre-masked query word, and computes the exact LCP only for rows that pass.
-// Each wave writes its per-chunk lists; a second kernel merges the chunks of
-// each query.
+// Before the scan, an LCP histogram of every query against the first rows
+// gives each query a starting limit, so most rows fail the filter from the
+// first tile on.  Each wave appends the entries of its per-chunk lists that can
+// still be in the answer to the query's compact partial list; a second kernel
+// merges them.
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -19,6 +22,7 @@ namespace lcpx {
 
 constexpr int kScanWaves = 4;
 constexpr int kScanUnroll = 4;
+constexpr int64_t kSeedChunkRows = kScanUnroll * kWave;  // one step of a block
 
 // Mask and masked query bits that a row's first two key words (as one 64-bit
 // value, word 0 high) must match for the row's rank key to beat `lim`
@@ -46,9 +50,85 @@ __device__ __forceinline__ void limit_filter(uint64_t lim, int64_t next_id, uint
     }
 }
 
-__global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Starting limits from the first S rows (ids 0..S-1).  hist[q][d] counts the
+// sample rows with LCP exactly d.  With t the largest d such that at least k'
+// sample rows have LCP >= d, those k' rows have keys <= rank_key(t, S - 1),
+// so the answer's k'-th key is below rank_key(t, S): every answer row beats
+// that key, which becomes the query's limit.  Block b counts part b % parts
+// of the sample for query b / parts.
+constexpr int kSeedThreads = 256;
+__global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const uint32_t* __restrict__ qkeys,
+                                                            int64_t S, int parts, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];                 // LCP 0..L, L <= 255
+    __shared__ uint32_t qw[128];                // key words of one query, W <= 128
+    const RowGeo g = ix.g;
+    const int lane = lane_id();
+    const int64_t qi = (int64_t)blockIdx.x / parts;
+    const int part = (int)((int64_t)blockIdx.x - qi * parts);
+    for (int i = threadIdx.x; i <= g.L; i += kSeedThreads) h[i] = 0;
+    for (int w = threadIdx.x; w < g.W; w += kSeedThreads) qw[w] = qkeys[qi * g.W + w];
+    __syncthreads();
+    const int64_t per = (S + parts - 1) / parts;
+    const int64_t r0 = (int64_t)part * per;
+    const int64_t r1 = r0 + per < S ? r0 + per : S;
+    for (int64_t base = r0; base < r1; base += kSeedThreads) {
+        const int64_t r = base + threadIdx.x;
+        const bool act = r < r1;
+        int lc = g.L;
+        if (act) {
+            const uint2 pw = ix.plane[r];
+            const uint32_t x0 = pw.x ^ qw[0];
+            const uint32_t x1 = g.W > 1 ? pw.y ^ qw[1] : 0u;
+            if (x0) {
+                lc = lcp_from_diff(0, x0, g);
+            } else if (x1) {
+                lc = lcp_from_diff(1, x1, g);
+            } else {
+                const uint32_t* row = ix.rows + r * g.W;
+                for (int w = 2; w < g.W; ++w) {
+                    const uint32_t x = row[w] ^ qw[w];
+                    if (x) {
+                        lc = lcp_from_diff(w, x, g);
+                        break;
+                    }
+                }
+            }
+        }
+        // one LDS add per distinct LCP value in the wave
+        uint64_t pending = ballot(act);
+        while (pending) {
+            const int v = readlane_i(lc, low_lane(pending));
+            const uint64_t same = ballot(((pending >> lane) & 1ull) && lc == v);
+            if (lane == low_lane(same)) atomicAdd(&h[v], (uint32_t)popc64(same));
+            pending &= ~same;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= g.L; i += kSeedThreads)
+        if (h[i]) atomicAdd(hist + qi * (g.L + 1) + i, h[i]);
+}
+
+__global__ void k_seed_limit(QueryBatch qb, int64_t N, int L, int64_t S, const uint32_t* __restrict__ hist,
+                             uint64_t* __restrict__ gthr) {
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= qb.Q) return;
+    const int k = query_k(qb, qi);
+    const int64_t kk = (int64_t)k < N ? (int64_t)k : N;
+    int64_t acc = 0;
+    uint64_t lim = kKeyMax;
+    for (int d = L; d >= 0; --d) {
+        acc += hist[qi * (L + 1) + d];
+        if (acc >= kk) {
+            lim = rank_key(d, (uint32_t)S);
+            break;
+        }
+    }
+    gthr[qi] = lim;
 }
 
 // gthr[q] holds the smallest k-th key any chunk has reached for query q: a row
@@ -77,12 +157,20 @@ __global__ void k_query_keys(QueryBatch qb, RowGeo g, uint32_t* __restrict__ qke
     qkeys[t] = key_word(qb.raw, qi * g.L, g, (int)(t - qi * g.W));
 }
 
-// Rows [row0, row_end) in chunks of chunk_rows; chunk c writes partial list
-// part0 + c of each query (nparts lists per query in total).
+// Blocks x < seed_chunks scan the sampled rows [0, seed_rows) in chunks of
+// seed_chunk_rows, normally one step (there the starting limit lets rows at
+// its LCP through, so that work is spread thin); the others scan
+// [seed_rows, N) in chunks of chunk_rows.
+// At the end each wave appends, per query, the entries of its list that do
+// not exceed the query's limit to the query's partial list (cap entries at
+// part + q * cap, fill count in cnt[q]); the append order does not matter,
+// the merge ranks by key.
 template <int NR, int TQ>
 __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, QueryBatch qb, const uint32_t* qkeys,
-                                                             int64_t row0, int64_t row_end, int64_t chunk_rows,
-                                                             int part0, int nparts, uint64_t* __restrict__ part,
+                                                             int64_t seed_rows, int seed_chunks,
+                                                             int64_t seed_chunk_rows, int64_t chunk_rows,
+                                                             int64_t cap, uint64_t* __restrict__ part,
+                                                             uint32_t* __restrict__ cnt,
                                                              uint64_t* __restrict__ gthr) {
     static_assert(kScanUnroll * TQ <= 64, "one flag bit per (tile, query)");
     extern __shared__ uint64_t s_dyn64[];
@@ -114,19 +202,23 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     ScanQueryState<NR>* st = st_all + wv * TQ;
     const uint32_t* qwords = s_q + wv * TQ * W;
 
-    const int64_t r_lo = row0 + (int64_t)blockIdx.x * chunk_rows;
-    const int64_t r_hi = r_lo + chunk_rows < row_end ? r_lo + chunk_rows : row_end;
-    const int second = W > 1 ? 1 : 0;                 // a one-word row has no second word:
-    const uint32_t second_mask = W > 1 ? ~0u : 0u;    // it reads word 0 again and masks it off
+    int64_t r_lo, r_hi;
+    if ((int)blockIdx.x < seed_chunks) {
+        r_lo = (int64_t)blockIdx.x * seed_chunk_rows;
+        r_hi = r_lo + seed_chunk_rows < seed_rows ? r_lo + seed_chunk_rows : seed_rows;
+    } else {
+        r_lo = seed_rows + (int64_t)((int)blockIdx.x - seed_chunks) * chunk_rows;
+        r_hi = r_lo + chunk_rows < N ? r_lo + chunk_rows : N;
+    }
     // rows of the next step are requested before the current step is
-    // processed, so a step's loads overlap the previous step's compute
-    uint32_t na[kScanUnroll], nb[kScanUnroll];
+    // tested, so a step's loads overlap the previous step's compute; one
+    // 8-byte load per row from the prefix plane (its second word is 0 for
+    // one-word rows).  Positions past the chunk re-read its last row.
+    uint2 nx[kScanUnroll];
 #pragma unroll
     for (int u = 0; u < kScanUnroll; ++u) {
         const int64_t id = r_lo + u * kWave + lane;
-        const uint32_t* r = ix.rows + (id < r_hi ? id : r_hi - 1) * W;
-        na[u] = r[0];
-        nb[u] = r[second];
+        nx[u] = ix.plane[id < r_hi ? id : r_hi - 1];
     }
     int it = 0;
     for (int64_t base = r_lo; base < r_hi; base += kScanUnroll * kWave, ++it) {
@@ -151,28 +243,19 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
             }
         }
         // first two key words of each lane's row (word 0 in the high half)
-        uint32_t wa[kScanUnroll], wb[kScanUnroll];
+        uint64_t w01[kScanUnroll];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            wa[u] = na[u];
-            wb[u] = nb[u];
-        }
+        for (int u = 0; u < kScanUnroll; ++u) w01[u] = ((uint64_t)nx[u].x << 32) | nx[u].y;
         if (base + kScanUnroll * kWave < r_hi) {
 #pragma unroll
             for (int u = 0; u < kScanUnroll; ++u) {
                 const int64_t id = base + (kScanUnroll + u) * kWave + lane;
-                const uint32_t* r = ix.rows + (id < r_hi ? id : r_hi - 1) * W;
-                na[u] = r[0];
-                nb[u] = r[second];
+                nx[u] = ix.plane[id < r_hi ? id : r_hi - 1];
             }
         }
-        uint64_t w01[kScanUnroll];
         uint64_t live[kScanUnroll];  // lanes holding a row of this chunk
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            w01[u] = ((uint64_t)wa[u] << 32) | (wb[u] & second_mask);
-            live[u] = ballot(base + u * kWave + lane < r_hi);
-        }
+        for (int u = 0; u < kScanUnroll; ++u) live[u] = ballot(base + u * kWave + lane < r_hi);
         // filters stay in VGPRs (wave-uniform values): one AND pair and one
         // 64-bit compare per (tile, query)
         uint64_t msk[TQ], qm[TQ];
@@ -238,29 +321,49 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         }
     }
 
+    // entries above a valid limit cannot be in the answer; each list is
+    // ascending, so the kept ones are a prefix.  Lane i counts query i's and
+    // reserves room for them with one atomic for all the wave's queries.
+    const uint64_t gl = lane < ntq ? gthr[q0i + lane] : 0ull;
+    int mine = 0;
 #pragma unroll 1
     for (int i = 0; i < ntq; ++i) {
         const int kk = st[i].kk;
-        uint64_t* dst = part + ((q0i + i) * nparts + part0 + blockIdx.x) * (int64_t)qb.k_max;
-        for (int e = lane; e < qb.k_max; e += kWave) dst[e] = e < kk ? st[i].list[e] : kKeyMax;
+        const uint64_t g_i = readlane64(gl, i);
+        const uint64_t keep = g_i < st[i].lim ? g_i : st[i].lim;
+        int n = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int e = r * kWave + lane;
+            const uint64_t v = st[i].list[e];
+            n += popc64(ballot(e < kk && v != kKeyMax && v <= keep));
+        }
+        mine = lane == i ? n : mine;
+    }
+    uint32_t at = 0;
+    if (lane < ntq && mine > 0) at = atomicAdd(cnt + q0i + lane, (uint32_t)mine);
+#pragma unroll 1
+    for (int i = 0; i < ntq; ++i) {
+        const int n = readlane_i(mine, i);
+        if (n == 0) continue;
+        uint64_t* dst = part + (q0i + i) * cap + (uint32_t)readlane_i((int)at, i);
+        for (int e = lane; e < n; e += kWave) dst[e] = st[i].list[e];
     }
 }
 
-// Merge partial lists [part_lo, part_hi) of each query.  With `limit` set,
-// write the k-th smallest merged key (kKeyMax if fewer than k) as the query's
-// starting limit instead of emitting the answer.
+// Merge each query's partial list (cnt[q] entries) into its answer.
 template <int NR>
-__global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb, int64_t N, int nparts, int part_lo,
-                                                                   int part_hi, const uint64_t* __restrict__ part,
-                                                                   uint64_t* __restrict__ limit) {
+__global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb, int64_t N, int64_t cap,
+                                                                   const uint64_t* __restrict__ part,
+                                                                   const uint32_t* __restrict__ cnt) {
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t qi = (int64_t)blockIdx.x * kScanWaves + wv;
     if (qi >= qb.Q) return;
     const int k = query_k(qb, qi);
     const int m = (int)((int64_t)k < N ? (int64_t)k : N);
-    const int64_t total = (int64_t)(part_hi - part_lo) * qb.k_max;
-    const uint64_t* src = part + (qi * nparts + part_lo) * (int64_t)qb.k_max;
+    const int64_t total = (int64_t)cnt[qi];
+    const uint64_t* src = part + qi * cap;
     WaveList<NR> lst;
     lst.init();
     constexpr int kMergeUnroll = 8;
@@ -269,8 +372,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
 #pragma unroll
         for (int u = 0; u < kMergeUnroll; ++u) {  // all loads in flight before any is used
             const int64_t t = b + u * kWave + lane;
-            const bool act = t < total && (int)(t % qb.k_max) < m;
-            key[u] = act ? src[t] : kKeyMax;
+            key[u] = t < total ? src[t] : kKeyMax;
         }
 #pragma unroll 1
         for (int u = 0; u < kMergeUnroll && b + u * kWave < total; ++u) {  // one copy of the offer code
@@ -279,11 +381,6 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
             for (int uu = 1; uu < kMergeUnroll; ++uu) x = u == uu ? key[uu] : x;
             lst.offer(x, x != kKeyMax, m);
         }
-    }
-    if (limit) {
-        const uint64_t kth = lst.get(m - 1);
-        if (lane == 0) limit[qi] = kth;
-        return;
     }
     int32_t* oid = qb.out_ids + query_off(qb, qi);
     int32_t* olc = qb.out_lcp + query_off(qb, qi);
@@ -316,11 +413,9 @@ static int tq_for(int nr, int64_t Q) {
     return tq;
 }
 
-// The first rows are scanned first, in seed chunks whose merged k-th key
-// becomes every query's starting limit for the remaining chunks.
+// Rows sampled for the starting limits, and the main pass's chunking.
 constexpr int64_t kChunkMinRows = 2048;
-constexpr int64_t kSeedChunkRows = kScanUnroll * kWave;  // one step per seed chunk
-constexpr int64_t kSeedRowsMax = 32768;
+constexpr int64_t kSeedRows = 32768;
 
 ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     ScanPlan p;
@@ -328,75 +423,97 @@ ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     p.tq = tq_for(p.nr, Q);
     const int64_t per_group = (int64_t)kScanWaves * p.tq;
     p.qgroups = (int)((Q + per_group - 1) / per_group);
+    p.seed_rows = N < kSeedRows ? N : kSeedRows;
+    // seed blocks per query: enough blocks in all to fill the device
+    const int64_t seed_tiles = (p.seed_rows + 255) / 256;
+    int64_t parts = Q > 0 ? 4096 / Q : 1;
+    if (parts > seed_tiles) parts = seed_tiles;
+    p.seed_parts = (int)(parts < 1 ? 1 : parts);
     const int64_t bytes_per_chunk = Q * (int64_t)k_max * 8;
     const int64_t max_by_mem = bytes_per_chunk > 0 ? ((int64_t)256 << 20) / bytes_per_chunk : 1;
-    // seed: up to 1/8 of the rows (at most kSeedRowsMax) in one-step chunks
-    p.seed_rows = N / 8 < kSeedRowsMax ? N / 8 : kSeedRowsMax;
-    p.seed_chunks = (int)(p.seed_rows / kSeedChunkRows);
-    if (p.seed_chunks > max_by_mem / 2) p.seed_chunks = (int)(max_by_mem / 2);
-    if (p.seed_chunks < 4) p.seed_chunks = 0;  // too few rows to be worth a seed
-    p.seed_rows = p.seed_chunks * kSeedChunkRows;
+    // sampled rows: one-step chunks while the grid stays near 4096 blocks,
+    // fewer and longer ones for many query groups or a tight partial budget
+    int64_t sc = (p.seed_rows + kSeedChunkRows - 1) / kSeedChunkRows;
+    const int64_t by_grid = 4096 / p.qgroups;
+    if (sc > by_grid) sc = by_grid;
+    if (sc > max_by_mem / 2) sc = max_by_mem / 2;
+    if (sc < 1) sc = 1;
+    p.seed_chunk_rows = (p.seed_rows + sc - 1) / sc;
+    p.seed_chunk_rows = (p.seed_chunk_rows + kSeedChunkRows - 1) / kSeedChunkRows * kSeedChunkRows;
+    p.seed_chunks = (int)((p.seed_rows + p.seed_chunk_rows - 1) / p.seed_chunk_rows);
+    // main: rows [seed_rows, N); aim for >= 4096 blocks (16 per CU), chunks of
+    // >= kChunkMinRows rows, partials <= 256 MiB
     const int64_t rest = N - p.seed_rows;
-    // main: aim for >= 4096 blocks (16 per CU), chunks of >= kChunkMinRows rows, partials <= 256 MiB
-    int64_t chunks = (4096 + p.qgroups - 1) / p.qgroups;
-    const int64_t max_by_rows = (rest + kChunkMinRows - 1) / kChunkMinRows;
-    if (chunks > max_by_rows) chunks = max_by_rows;
-    if (chunks > max_by_mem - p.seed_chunks) chunks = max_by_mem - p.seed_chunks;
-    if (chunks > 65535) chunks = 65535;
-    if (chunks < 1) chunks = 1;
-    const int64_t step = (int64_t)kScanUnroll * kWave;
-    int64_t rows = (rest + chunks - 1) / chunks;
-    rows = (rows + step - 1) / step * step;
-    p.chunk_rows = rows;
-    p.chunks = (int)((rest + rows - 1) / rows);
+    if (rest <= 0) {
+        p.chunk_rows = kChunkMinRows;
+        p.chunks = 0;
+    } else {
+        int64_t chunks = (4096 + p.qgroups - 1) / p.qgroups;
+        const int64_t max_by_rows = (rest + kChunkMinRows - 1) / kChunkMinRows;
+        if (chunks > max_by_rows) chunks = max_by_rows;
+        if (chunks > max_by_mem - p.seed_chunks) chunks = max_by_mem - p.seed_chunks;
+        if (chunks > 65535 - p.seed_chunks) chunks = 65535 - p.seed_chunks;
+        if (chunks < 1) chunks = 1;
+        const int64_t step = (int64_t)kScanUnroll * kWave;
+        int64_t rows = (rest + chunks - 1) / chunks;
+        rows = (rows + step - 1) / step * step;
+        p.chunk_rows = rows;
+        p.chunks = (int)((rest + rows - 1) / rows);
+    }
     p.nparts = p.seed_chunks + p.chunks;
     return p;
 }
 
-size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, int W) {
-    // per-chunk lists, one shared limit per query, then the query key words
-    return (size_t)Q * (size_t)p.nparts * (size_t)k_max + (size_t)Q + ((size_t)Q * W + 1) / 2;
+ScanScratch scan_scratch(const ScanPlan& p, int64_t Q, int32_t k_max, const RowGeo& g, uint64_t* base) {
+    ScanScratch sc;
+    sc.cap = (int64_t)p.nparts * k_max;
+    sc.part = base;
+    sc.gthr = base + (size_t)Q * (size_t)sc.cap;
+    uint32_t* u = reinterpret_cast<uint32_t*>(sc.gthr + Q);
+    sc.cnt = u;                                // [Q]      zeroed per call
+    sc.hist = u + Q;                           // [Q][L+1] zeroed per call
+    sc.qkeys = sc.hist + (size_t)Q * (g.L + 1);  // [Q][W]
+    sc.words = ((size_t)Q * (size_t)sc.cap + (size_t)Q) * 2 + (size_t)Q * (1 + (g.L + 1) + g.W);
+    return sc;
+}
+
+size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, const RowGeo& g) {
+    return (scan_scratch(p, Q, k_max, g, nullptr).words + 1) / 2;
 }
 
 template <int NR, int TQ>
-static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* part,
+static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, const ScanScratch& sc,
                           hipStream_t s) {
     const size_t shm =
         (size_t)kScanWaves * TQ * (sizeof(ScanQueryState<NR>) + (size_t)ix.g.W * sizeof(uint32_t));
-    uint64_t* gthr = part + (size_t)qb.Q * (size_t)p.nparts * (size_t)qb.k_max;
-    const uint32_t* qkeys = reinterpret_cast<const uint32_t*>(gthr + qb.Q);
-    const dim3 blk(kScanWaves * kWave);
-    if (p.seed_chunks > 0) {
-        hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)p.seed_chunks, (unsigned)p.qgroups), blk, shm, s, ix, qb,
-                           qkeys, (int64_t)0, p.seed_rows, kSeedChunkRows, 0, p.nparts, part, gthr);
-        hipLaunchKernelGGL((k_scan_merge<NR>), dim3((unsigned)((qb.Q + kScanWaves - 1) / kScanWaves)), blk, 0, s, qb,
-                           ix.N, p.nparts, 0, p.seed_chunks, part, gthr);
-    }
-    hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)p.chunks, (unsigned)p.qgroups), blk, shm, s, ix, qb, qkeys,
-                       p.seed_rows, ix.N, p.chunk_rows, p.seed_chunks, p.nparts, part, gthr);
+    hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)p.nparts, (unsigned)p.qgroups), dim3(kScanWaves * kWave), shm,
+                       s, ix, qb, sc.qkeys, p.seed_rows, p.seed_chunks, p.seed_chunk_rows, p.chunk_rows, sc.cap,
+                       sc.part, sc.cnt, sc.gthr);
 }
 
-hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* part, hipStream_t s,
+hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* scratch, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
     if (qb.Q <= 0) return hipSuccess;
+    const ScanScratch sc = scan_scratch(p, qb.Q, qb.k_max, ix.g, scratch);
+    const int64_t nz = qb.Q * (int64_t)(1 + ix.g.L + 1);  // cnt and hist
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, sc.cnt, nz, 0u);
+    hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((qb.Q * ix.g.W + 255) / 256)), dim3(256), 0, s, qb, ix.g,
+                       sc.qkeys);
+    hipLaunchKernelGGL(k_seed_hist, dim3((unsigned)(qb.Q * p.seed_parts)), dim3(kSeedThreads), 0, s, ix, sc.qkeys,
+                       p.seed_rows, p.seed_parts, sc.hist);
+    hipLaunchKernelGGL(k_seed_limit, dim3((unsigned)((qb.Q + 255) / 256)), dim3(256), 0, s, qb, ix.N, ix.g.L,
+                       p.seed_rows, sc.hist, sc.gthr);
     if (ev0) hipEventRecord(ev0, s);
-    {
-        uint64_t* gthr = part + (size_t)qb.Q * (size_t)p.nparts * (size_t)qb.k_max;
-        uint32_t* qkeys = reinterpret_cast<uint32_t*>(gthr + qb.Q);
-        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((qb.Q + 255) / 256)), dim3(256), 0, s, gthr, qb.Q, kKeyMax);
-        hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((qb.Q * ix.g.W + 255) / 256)), dim3(256), 0, s, qb, ix.g,
-                           qkeys);
-    }
     switch (p.nr * 100 + p.tq) {
-        case 108: launch_scan_t<1, 8>(ix, qb, p, part, s); break;
-        case 104: launch_scan_t<1, 4>(ix, qb, p, part, s); break;
-        case 101: launch_scan_t<1, 1>(ix, qb, p, part, s); break;
-        case 208: launch_scan_t<2, 8>(ix, qb, p, part, s); break;
-        case 204: launch_scan_t<2, 4>(ix, qb, p, part, s); break;
-        case 201: launch_scan_t<2, 1>(ix, qb, p, part, s); break;
-        case 404: launch_scan_t<4, 4>(ix, qb, p, part, s); break;
-        case 401: launch_scan_t<4, 1>(ix, qb, p, part, s); break;
-        case 1601: launch_scan_t<16, 1>(ix, qb, p, part, s); break;
+        case 108: launch_scan_t<1, 8>(ix, qb, p, sc, s); break;
+        case 104: launch_scan_t<1, 4>(ix, qb, p, sc, s); break;
+        case 101: launch_scan_t<1, 1>(ix, qb, p, sc, s); break;
+        case 208: launch_scan_t<2, 8>(ix, qb, p, sc, s); break;
+        case 204: launch_scan_t<2, 4>(ix, qb, p, sc, s); break;
+        case 201: launch_scan_t<2, 1>(ix, qb, p, sc, s); break;
+        case 404: launch_scan_t<4, 4>(ix, qb, p, sc, s); break;
+        case 401: launch_scan_t<4, 1>(ix, qb, p, sc, s); break;
+        case 1601: launch_scan_t<16, 1>(ix, qb, p, sc, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
@@ -405,14 +522,12 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
     const unsigned grid = (unsigned)((qb.Q + kScanWaves - 1) / kScanWaves);
     const dim3 blk(kScanWaves * kWave);
     switch (p.nr) {
-        case 1: hipLaunchKernelGGL((k_scan_merge<1>), dim3(grid), blk, 0, s, qb, ix.N, p.nparts, 0, p.nparts, part,
-                                   (uint64_t*)nullptr); break;
-        case 2: hipLaunchKernelGGL((k_scan_merge<2>), dim3(grid), blk, 0, s, qb, ix.N, p.nparts, 0, p.nparts, part,
-                                   (uint64_t*)nullptr); break;
-        case 4: hipLaunchKernelGGL((k_scan_merge<4>), dim3(grid), blk, 0, s, qb, ix.N, p.nparts, 0, p.nparts, part,
-                                   (uint64_t*)nullptr); break;
-        default: hipLaunchKernelGGL((k_scan_merge<16>), dim3(grid), blk, 0, s, qb, ix.N, p.nparts, 0, p.nparts, part,
-                                    (uint64_t*)nullptr); break;
+        case 1: hipLaunchKernelGGL((k_scan_merge<1>), dim3(grid), blk, 0, s, qb, ix.N, sc.cap, sc.part, sc.cnt); break;
+        case 2: hipLaunchKernelGGL((k_scan_merge<2>), dim3(grid), blk, 0, s, qb, ix.N, sc.cap, sc.part, sc.cnt); break;
+        case 4: hipLaunchKernelGGL((k_scan_merge<4>), dim3(grid), blk, 0, s, qb, ix.N, sc.cap, sc.part, sc.cnt); break;
+        default:
+            hipLaunchKernelGGL((k_scan_merge<16>), dim3(grid), blk, 0, s, qb, ix.N, sc.cap, sc.part, sc.cnt);
+            break;
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -4,9 +4,10 @@ The paper reports energy per query for the full scan and for range scans over
 prefix buckets (section 6, Theorem "TAL Energy Reduction"; section 7, Table
 "TAL range-scan vs full-scan" and the bucket-count figure), sampled from the
 board's power telemetry.  Here the socket energy accumulator of the MI355X is
-read before and after a sustained run of one path; joules over the run divided
-by the queries answered is the energy per query.  The idle draw over the same
-length of time is measured too, so the dynamic share can be told apart.
+read while one path runs without pause; it advances in coarse steps, so the
+power is taken between two of its update edges and divided by the query rate
+over the same interval.  The idle draw is measured the same way, so the
+dynamic share can be told apart.
 
 amd-smi ships with ROCm as a Python package outside site-packages; when it is
 missing, or the driver refuses the query, `EnergyMeter` raises
@@ -49,6 +50,14 @@ def _bdf_of(device: torch.device) -> str:
     return f"{p.pci_domain_id:04x}:{p.pci_bus_id:02x}:{p.pci_device_id:02x}".lower()
 
 
+def _span(ts0: int, ts1: int, h0: float, h1: float) -> float:
+    """Seconds between two accumulator updates: their own timestamps (ns)
+    when those agree with the host clock to within a factor of two."""
+    host = h1 - h0
+    dev = (ts1 - ts0) * 1e-9
+    return dev if 0.5 * host <= dev <= 2.0 * host else host
+
+
 class EnergyMeter:
     """Energy accumulator of the socket that holds `device`."""
 
@@ -82,45 +91,73 @@ class EnergyMeter:
             raise EnergyUnavailable(f"device {want} not among amd-smi devices {bdfs}")
         self.read_joules()  # fail here, not in the middle of a measurement
 
-    def read_joules(self) -> float:
+    def _read(self):
         try:
             r = self._smi.amdsmi_get_energy_count(self.handle)
         except Exception as e:
             raise EnergyUnavailable(f"amdsmi_get_energy_count failed: {e}") from None
-        # accumulator ticks x resolution (microjoules per tick)
-        return float(r["energy_accumulator"]) * float(r["counter_resolution"]) * 1e-6
+        # accumulator ticks x resolution (microjoules per tick); timestamp in ns
+        return float(r["energy_accumulator"]) * float(r["counter_resolution"]) * 1e-6, int(r["timestamp"])
 
-    def measure(self, fn: Callable[[], int], seconds: float, sync_every: int = 8) -> Dict:
-        """Call `fn` (which returns the queries it answered) repeatedly for at
-        least `seconds` of wall time; return joules, seconds, watts, queries and
-        J/query for the run."""
+    def read_joules(self) -> float:
+        return self._read()[0]
+
+    def measure(self, fn: Callable[[], int], seconds: float, sync_every: int = 8, max_wait_s: float = 5.0) -> Dict:
+        """Run `fn` (which returns the queries it answered) without pause and
+        time it between two updates of the energy accumulator at least
+        `seconds` apart.  The accumulator advances in coarse steps, so the
+        energy is taken between update edges, over the accumulator's own
+        timestamps, and the query rate over the host clock between the moments
+        the edges were seen.  Returns watts, queries/s and J/query."""
         torch.cuda.synchronize(self.device)
-        e0 = self.read_joules()
-        t0 = time.perf_counter()
-        queries = 0
+        e_prev, _ = self._read()
         calls = 0
+        queries = 0
+        edges = []  # (joules, counter timestamp ns, host s, queries done)
+        t_begin = time.perf_counter()
         while True:
             queries += int(fn())
             calls += 1
-            if calls % sync_every == 0:
-                torch.cuda.synchronize(self.device)
-                if time.perf_counter() - t0 >= seconds:
+            if calls % sync_every:
+                continue
+            torch.cuda.synchronize(self.device)
+            now = time.perf_counter()
+            e, ts = self._read()
+            if e != e_prev:
+                edges.append((e, ts, now, queries))
+                e_prev = e
+                if len(edges) >= 2 and now - edges[0][2] >= seconds:
                     break
-        t1 = time.perf_counter()
-        e1 = self.read_joules()
-        j = e1 - e0
-        dt = t1 - t0
-        return {"joules": round(j, 3), "seconds": round(dt, 3), "watts": round(j / dt, 1),
-                "queries": queries, "calls": calls,
-                "j_per_query": (j / queries) if queries else None}
+            if now - t_begin > seconds + max_wait_s:
+                break
+        if len(edges) < 2:
+            return {"error": "the energy accumulator did not advance during the run", "calls": calls}
+        (e0, ts0, h0, q0), (e1, ts1, h1, q1) = edges[0], edges[-1]
+        span_s = _span(ts0, ts1, h0, h1)
+        watts = (e1 - e0) / span_s
+        qps = (q1 - q0) / (h1 - h0)
+        return {"watts": round(watts, 1), "seconds": round(h1 - h0, 3), "queries_per_s": round(qps, 1),
+                "j_per_query": watts / qps if qps > 0 else None, "accumulator_updates": len(edges) - 1}
 
-    def idle_watts(self, seconds: float) -> float:
+    def idle_watts(self, seconds: float, max_wait_s: float = 5.0) -> Optional[float]:
+        """Average power with the GPU idle, between accumulator updates."""
         torch.cuda.synchronize(self.device)
-        e0 = self.read_joules()
-        t0 = time.perf_counter()
-        time.sleep(seconds)
-        e1 = self.read_joules()
-        return (e1 - e0) / (time.perf_counter() - t0)
+        e_prev, _ = self._read()
+        edges = []
+        t_begin = time.perf_counter()
+        while time.perf_counter() - t_begin < seconds + max_wait_s:
+            time.sleep(0.002)
+            e, ts = self._read()
+            if e != e_prev:
+                edges.append((e, ts, time.perf_counter()))
+                e_prev = e
+                if len(edges) >= 2 and edges[-1][2] - edges[0][2] >= seconds:
+                    break
+        if len(edges) < 2:
+            return None
+        (e0, ts0, h0), (e1, ts1, h1) = edges[0], edges[-1]
+        span_s = _span(ts0, ts1, h0, h1)
+        return (e1 - e0) / span_s
 
     def close(self) -> None:
         try:
