@@ -232,8 +232,11 @@ def main():
         uo = (torch.empty(int(ku.sum()), dtype=torch.int32, device=dev),
               torch.empty(int(ku.sum()), dtype=torch.int32, device=dev))
         tune = batching.tune_launch(idx, q_dev, ku, reps=5)
-        cl = batching.CapturedLaunch(idx, cap_queries=w.Q, k_max=100, blocks=tune["best"].blocks
-                                     if tune["best"].mode == "persistent" else 0)
+        best = tune["best"] if tune["best"].mode != "plain" else min(
+            (sh for sh in tune["tried"] if sh.mode != "plain"), key=lambda sh: sh.ms)
+        tune["best"] = best
+        cl = batching.CapturedLaunch(idx, cap_queries=w.Q, k_max=100,
+                                     blocks=best.blocks if best.mode == "persistent" else 0)
 
         def timed(fn, reps=20):
             fn()
@@ -244,17 +247,41 @@ def main():
             torch.cuda.synchronize()
             return (time.perf_counter() - t) * 1e3 / reps
 
+        def device_ms(fn, stream, reps=20):
+            # GPU time of `reps` back-to-back calls, from events on `stream`
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            b.synchronize()
+            return a.elapsed_time(b) / reps
+
         one = timed(lambda: idx.topk(q_dev, ku, out=uo))
         per_bucket = timed(lambda: [idx.topk(bq[kv], kv, out=bout[kv]) for kv in buckets])
-        captured = timed(lambda: cl.run(q_dev, ku))
+        cur = torch.cuda.current_stream()
+        per_bucket_dev = device_ms(lambda: [idx.topk(bq[kv], kv, out=bout[kv]) for kv in buckets], cur)
+        cl.q.copy_(q_dev)  # the batch is produced straight into the captured query buffer
+        torch.cuda.synchronize()
+        captured = timed(lambda: cl.run(None, ku, n=w.Q))
+        reps_c = 20
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps_c)]
+        for e in evs:
+            cl.run(None, ku, n=w.Q, events=e)
+        torch.cuda.synchronize()
+        captured_dev = float(np.median([a.elapsed_time(b) for a, b in evs]))
         ref = idx.topk(q_dev, ku, out=uo)
-        gi, gl, _ = cl.run(q_dev, ku)
+        gi, gl, _ = cl.run(None, ku, n=w.Q)
         torch.cuda.synchronize()
         same = bool(torch.equal(gi, ref.ids) and torch.equal(gl, ref.lcps))
         uneven = {"queries": w.Q, "k_choices": [1, 10, 100],
                   "one_plain_launch_ms": round(one, 4), "per_k_bucket_launches_ms": round(per_bucket, 4),
-                  "captured_persistent_ms": round(captured, 4),
-                  "captured_persistent_qps": round(w.Q / (captured * 1e-3), 1),
+                  "per_k_bucket_launches_gpu_ms": round(per_bucket_dev, 4),
+                  "captured_ms": round(captured, 4), "captured_gpu_ms": round(captured_dev, 4),
+                  "captured_shape": (tune["best"].mode, tune["best"].blocks),
+                  "captured_qps": round(w.Q / (captured * 1e-3), 1),
                   "autotune": [(sh.mode, sh.blocks, round(sh.ms, 4)) for sh in tune["tried"]],
                   "captured_equals_plain": same}
         log(args, f"[bench] uneven batch: {uneven}")

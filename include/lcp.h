@@ -149,24 +149,30 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
 lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, void* stream);
 
 /*
- * Persistent, graph-capturable form of lcp_topk_dev for batches of uneven
- * size and k: one launch of `blocks` workgroups (4 waves each; blocks <= 0
- * picks one that fills the device) whose waves take queries from a device
- * work counter until *q_count_dev queries are done.  The batch size is read
- * on the device, so a HIP graph captured once replays for any batch up to the
- * capacity of the buffers it was captured with.  Answers are those of
- * lcp_topk_dev (bit-identical; the order in which waves take queries does not
- * reach the output).
+ * Graph-capturable form of lcp_topk_dev for batches of uneven size and k:
+ * the batch size is read on the device, so a HIP graph captured once replays
+ * for any batch up to the capacity of the buffers it was captured with.  The
+ * launch has `blocks` workgroups of 4 waves; wave w answers query w, and when
+ * the grid has fewer waves than the batch has queries, waves then take
+ * further queries from a device work counter (the persistent form).  Answers
+ * are those of lcp_topk_dev (bit-identical; which wave answers a query does
+ * not reach the output).
  *
- *   q_count_dev : device int64, number of queries of this launch (0..Q_cap).
+ *   q_capacity  : largest batch size any launch of this call (or of a graph
+ *                 captured from it) may see; 1 <= q_capacity < 2^31.  The
+ *                 queries, k_dev, off_dev and output buffers hold that many.
+ *   q_count_dev : device int64, number of queries of this launch
+ *                 (0..q_capacity).
  *   k_dev, off_dev, k_max : as lcp_topk_dev (k_max bounds every k of any
  *                 batch replayed through a captured graph).
+ *   blocks      : <= 0 picks ceil(q_capacity / 4), one wave per query and no
+ *                 work counter; fewer blocks make waves loop over queries.
  * Capture: make one call on the stream first (it sets up the stream's work
- * counter); the call itself allocates nothing and never synchronises.
+ * counter); the call itself then allocates nothing and never synchronises.
  */
-lcp_status lcp_topk_persistent(const lcp_index* index, const void* queries, const int64_t* q_count_dev,
-                               const int32_t* k_dev, const int64_t* off_dev, int32_t k_max, int32_t* out_ids,
-                               int32_t* out_lcp, int32_t blocks, void* stream);
+lcp_status lcp_topk_persistent(const lcp_index* index, const void* queries, int64_t q_capacity,
+                               const int64_t* q_count_dev, const int32_t* k_dev, const int64_t* off_dev,
+                               int32_t k_max, int32_t* out_ids, int32_t* out_lcp, int32_t blocks, void* stream);
 
 /* Synchronise every stream the index has been used on, then free it.  NULL is a no-op. */
 void lcp_index_free(lcp_index* index);

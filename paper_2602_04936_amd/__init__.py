@@ -49,7 +49,7 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_index_views": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)],
         "lcp_scan_info": [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "lcp_index_append": [vp, vp, i64, vp],
-        "lcp_topk_persistent": [vp, vp, vp, vp, vp, i32, vp, vp, i32, vp],
+        "lcp_topk_persistent": [vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, vp],
         "lcp_set_kernel_timing": [vp, i32],
         "lcp_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -180,11 +180,15 @@ class Index:
     def topk_persistent(self, queries: torch.Tensor, q_count_dev: torch.Tensor, k_dev: torch.Tensor,
                         off_dev: torch.Tensor, k_max: int, out_ids: torch.Tensor, out_lcp: torch.Tensor,
                         blocks: int = 0, stream=None):
-        """Persistent, graph-capturable launch (lcp_topk_persistent); the batch size is *q_count_dev."""
+        """Graph-capturable launch (lcp_topk_persistent); the batch size is *q_count_dev, at most
+        the capacity queries.shape[0] (k_dev and off_dev hold at least that many entries)."""
         q = _token_tensor(queries, self.token_bytes)
         if q_count_dev.dtype != torch.int64 or k_dev.dtype != torch.int32 or off_dev.dtype != torch.int64:
             raise TypeError("q_count_dev and off_dev must be int64, k_dev int32")
-        _check(lib.lcp_topk_persistent(self._h, q.data_ptr(), q_count_dev.data_ptr(), k_dev.data_ptr(),
+        cap = int(q.shape[0])
+        if k_dev.numel() < cap or off_dev.numel() < cap + 1:
+            raise ValueError(f"k_dev and off_dev must hold {cap} and {cap + 1} entries")
+        _check(lib.lcp_topk_persistent(self._h, q.data_ptr(), cap, q_count_dev.data_ptr(), k_dev.data_ptr(),
                                        off_dev.data_ptr(), int(k_max), out_ids.data_ptr(), out_lcp.data_ptr(),
                                        int(blocks), _stream_handle(stream)))
 

@@ -1,16 +1,17 @@
-"""Uneven query batches in one persistent, HIP-graph-captured launch.
+"""Uneven query batches in one HIP-graph-captured launch.
 
 A batch mixes queries of different k (and, through the data, tied blocks of
-very different lengths).  `CapturedLaunch` captures one persistent index-path
-launch (`lcp_topk_persistent`: a grid that fills the device, waves taking
-queries from a device counter, the batch size read on the device) into a HIP
-graph over fixed buffers; each batch is copied into those buffers and the graph
-is replayed, so a launch costs one graph replay whatever its size (up to the
-capacity) and its mix of k.
+very different lengths).  `CapturedLaunch` captures one device-counted
+index-path launch (`lcp_topk_persistent`: the batch size is read on the
+device) into a HIP graph over fixed buffers; each batch is copied into those
+buffers and the graph is replayed, so a launch costs one graph replay whatever
+its size (up to the capacity) and its mix of k.  By default the captured grid
+has one wave per query of the capacity; a smaller persistent grid, whose waves
+loop over queries from a device work counter, can be chosen instead.
 
-`tune_launch` is the autotuner: it times the plain launch (one wave per query)
-and persistent launches of several grid sizes on a sample batch and returns
-the fastest shape.
+`tune_launch` is the autotuner: it times the plain launch, the one-wave-per-
+query counted launch and persistent grids of several sizes on a sample batch
+and returns the fastest shape.
 """
 from __future__ import annotations
 
@@ -25,17 +26,19 @@ __all__ = ["CapturedLaunch", "LaunchShape", "tune_launch", "split_by_k"]
 
 @dataclasses.dataclass
 class LaunchShape:
-    mode: str          # "plain" (one wave per query) or "persistent"
-    blocks: int = 0    # persistent grid size (0 = library default)
+    mode: str          # "plain", "counted" (one wave per query) or "persistent" (waves loop)
+    blocks: int = 0    # grid size in blocks of 4 waves (0 = one wave per query)
     ms: float = float("nan")
 
 
 class CapturedLaunch:
-    """Persistent index-path launch captured once, replayed per batch.
+    """Device-counted index-path launch captured once, replayed per batch.
 
-    cap_queries : largest batch; k_max : largest k any batch may use.
-    The object owns its stream; replays run on that stream and must not
-    overlap each other (they share the device work counter).
+    cap_queries : largest batch; k_max : largest k any batch may use;
+    blocks : 0 for one wave per query of the capacity, else a persistent grid.
+    The object owns its stream; replays run on that stream in order.  Per-batch
+    k, offsets and size go up in one copy from one of two pinned staging
+    buffers, so the host fills the next batch while the previous one runs.
     """
 
     def __init__(self, index, cap_queries: int, k_max: int, blocks: int = 0):
@@ -46,17 +49,20 @@ class CapturedLaunch:
         qdt = torch.uint8 if index.token_bytes == 1 else torch.int16
         self.stream = torch.cuda.Stream(device=dev)
         self.q = torch.zeros((self.cap, index.L), dtype=qdt, device=dev)
-        self.k = torch.ones(self.cap, dtype=torch.int32, device=dev)
-        self.off = torch.zeros(self.cap + 1, dtype=torch.int64, device=dev)
-        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        # staging layout (bytes): [count int64][off int64 x (cap+1)][k int32 x cap]
+        self._nbytes = 8 + 8 * (self.cap + 1) + 4 * self.cap
+        self.dbuf = torch.zeros(self._nbytes, dtype=torch.uint8, device=dev)
+        self.count, self.off, self.k = self._views(self.dbuf)
+        self.k.fill_(1)
+        self.hbufs = [torch.zeros(self._nbytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        self.hviews = [self._views(h) for h in self.hbufs]
+        self.staged = [torch.cuda.Event(), torch.cuda.Event()]  # copy out of pinned buffer i done
+        for e in self.staged:
+            e.record(torch.cuda.current_stream(dev))
+        self.turn = 0
         self.ids = torch.empty(self.cap * self.k_max, dtype=torch.int32, device=dev)
         self.lcps = torch.empty(self.cap * self.k_max, dtype=torch.int32, device=dev)
-        self.k_host = torch.empty(self.cap, dtype=torch.int32, pin_memory=True)
-        self.off_host = torch.empty(self.cap + 1, dtype=torch.int64, pin_memory=True)
-        self.count_host = torch.empty(1, dtype=torch.int64, pin_memory=True)
         self.blocks = int(blocks)
-        self.staged = torch.cuda.Event()  # the last run's copies out of the pinned staging have run
-        self.staged.record(torch.cuda.current_stream(dev))
         torch.cuda.synchronize(dev)
         with torch.cuda.stream(self.stream):  # first call on the stream sets up its work counter
             self._launch()
@@ -66,39 +72,49 @@ class CapturedLaunch:
             self._launch()
         self.stream.synchronize()
 
+    def _views(self, buf):
+        c = 8 + 8 * (self.cap + 1)
+        return buf[0:8].view(torch.int64), buf[8:c].view(torch.int64), buf[c:c + 4 * self.cap].view(torch.int32)
+
     def _launch(self):
         self.index.topk_persistent(self.q, self.count, self.k, self.off, self.k_max, self.ids, self.lcps,
                                    blocks=self.blocks, stream=self.stream)
 
-    def run(self, queries: torch.Tensor, k) -> "tuple[torch.Tensor, torch.Tensor, np.ndarray]":
+    def run(self, queries: Optional[torch.Tensor], k, n: Optional[int] = None,
+            events=None) -> "tuple[torch.Tensor, torch.Tensor, np.ndarray]":
         """Answer `queries` (device [n, L]) with per-query k (host); returns
-        (ids, lcps, offsets) views valid until the next run."""
-        n = int(queries.shape[0])
+        (ids, lcps, offsets) views valid until the next run.  With queries
+        None the first n rows of `self.q`, filled by the caller, are used.
+        `events` = (start, end) are recorded around the device work."""
+        n = int(queries.shape[0]) if queries is not None else int(n)
         if n > self.cap:
             raise ValueError(f"batch of {n} exceeds the captured capacity {self.cap}")
         ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (n,)))
         if n and (ks.min() < 1 or ks.max() > self.k_max):
             raise ValueError(f"k must lie in [1, {self.k_max}]")
-        self.staged.synchronize()  # the previous run may still be reading the pinned staging
-        kh = self.k_host.numpy()
-        oh = self.off_host.numpy()
-        kh[:n] = ks
-        oh[0] = 0
-        np.cumsum(ks, out=oh[1:n + 1])
-        self.count_host.numpy()[0] = n
+        t = self.turn
+        self.turn ^= 1
+        self.staged[t].synchronize()  # the copy of two runs ago has left this buffer
+        hc, ho, hk = (v.numpy() for v in self.hviews[t])
+        hc[0] = n
+        ho[0] = 0
+        np.cumsum(ks, out=ho[1:n + 1])
+        hk[:n] = ks
         cur = torch.cuda.current_stream()
         self.stream.wait_stream(cur)  # the queries were produced on the caller's stream
         with torch.cuda.stream(self.stream):
-            if n:
+            if events is not None:
+                events[0].record(self.stream)
+            if n and queries is not None:
                 self.q[:n].copy_(queries, non_blocking=True)
-                self.k[:n].copy_(self.k_host[:n], non_blocking=True)
-                self.off[:n + 1].copy_(self.off_host[:n + 1], non_blocking=True)
-            self.count.copy_(self.count_host, non_blocking=True)
-            self.staged.record(self.stream)
+            self.dbuf.copy_(self.hbufs[t], non_blocking=True)
+            self.staged[t].record(self.stream)
             self.graph.replay()
+            if events is not None:
+                events[1].record(self.stream)
         cur.wait_stream(self.stream)
-        total = int(oh[n])
-        return self.ids[:total], self.lcps[:total], oh[:n + 1].copy()
+        total = int(ho[n])
+        return self.ids[:total], self.lcps[:total], ho[:n + 1].copy()
 
 
 def _time_ms(fn, reps: int) -> float:
@@ -116,8 +132,9 @@ def _time_ms(fn, reps: int) -> float:
 
 
 def tune_launch(index, queries: torch.Tensor, k, reps: int = 7, cus: Optional[int] = None) -> Dict:
-    """Time the plain launch and persistent launches of several grid sizes on
-    one batch; return {"best": LaunchShape, "tried": [LaunchShape, ...]}."""
+    """Time the plain launch, the one-wave-per-query counted launch and
+    persistent grids of 1, 2 and 4 blocks per CU on one batch; return
+    {"best": LaunchShape, "tried": [LaunchShape, ...]}."""
     n = int(queries.shape[0])
     ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (n,)))
     kmax = int(ks.max())
@@ -134,8 +151,12 @@ def tune_launch(index, queries: torch.Tensor, k, reps: int = 7, cus: Optional[in
     tried: List[LaunchShape] = []
     tried.append(LaunchShape("plain", 0, _time_ms(
         lambda: index.topk_dev(queries, k_dev, off_dev, kmax, ids, lcps), reps)))
-    for mult in (1, 2, 4, 6):
+    tried.append(LaunchShape("counted", 0, _time_ms(
+        lambda: index.topk_persistent(queries, count, k_dev, off_dev, kmax, ids, lcps, blocks=0), reps)))
+    for mult in (1, 2, 4):
         b = cus * mult
+        if 4 * b >= n:
+            continue  # that grid is the counted launch
         tried.append(LaunchShape("persistent", b, _time_ms(
             lambda: index.topk_persistent(queries, count, k_dev, off_dev, kmax, ids, lcps, blocks=b), reps)))
     best = min(tried, key=lambda s: s.ms)

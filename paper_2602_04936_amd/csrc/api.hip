@@ -552,10 +552,12 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
     return query_dev(index, Path::Scan, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, stream);
 }
 
-lcp_status lcp_topk_persistent(const lcp_index* idx, const void* queries, const int64_t* q_count_dev,
-                               const int32_t* k_dev, const int64_t* off_dev, int32_t k_max, int32_t* out_ids,
-                               int32_t* out_lcp, int32_t blocks, void* stream) {
+lcp_status lcp_topk_persistent(const lcp_index* idx, const void* queries, int64_t q_capacity,
+                               const int64_t* q_count_dev, const int32_t* k_dev, const int64_t* off_dev, int32_t k_max,
+                               int32_t* out_ids, int32_t* out_lcp, int32_t blocks, void* stream) {
     if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (q_capacity < 1 || q_capacity > INT32_MAX)
+        return fail(LCP_EINVAL, "q_capacity = %lld is outside [1, 2^31)", (long long)q_capacity);
     if (!queries || !q_count_dev || !k_dev || !off_dev || !out_ids || !out_lcp)
         return fail(LCP_EINVAL, "NULL device pointer");
     if (k_max < 1 || k_max > LCP_K_MAX) return fail(LCP_EINVAL, "k_max = %d is outside [1, %d]", k_max, LCP_K_MAX);
@@ -565,8 +567,10 @@ lcp_status lcp_topk_persistent(const lcp_index* idx, const void* queries, const 
     lcp_status st = get_ctx(idx, s, &c);
     if (st != LCP_OK) return st;
     if (!c->d_counter) HIP_TRY(hipMalloc(&c->d_counter, sizeof(unsigned long long)));
-    // 6 resident waves per SIMD, 4 SIMDs per CU, 4 waves per block
-    const int b = blocks > 0 ? blocks : idx->cus * 6;
+    // blocks <= 0: one wave per query of the capacity
+    const int64_t cover = (q_capacity + 3) / 4;
+    const int b = blocks > 0 ? blocks : (int)cover;
+    const bool looping = (int64_t)b < cover;
     QueryBatch qb;
     qb.raw = queries;
     qb.Q = 0;  // read on the device
@@ -577,7 +581,7 @@ lcp_status lcp_topk_persistent(const lcp_index* idx, const void* queries, const 
     qb.k_max = k_max;
     qb.out_ids = out_ids;
     qb.out_lcp = out_lcp;
-    HIP_TRY(launch_index_query_persistent(idx->view(), qb, q_count_dev, c->d_counter, b, s));
+    HIP_TRY(launch_index_query_persistent(idx->view(), qb, q_count_dev, c->d_counter, b, looping, s));
     return LCP_OK;
 }
 

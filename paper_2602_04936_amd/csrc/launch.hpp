@@ -86,10 +86,12 @@ __device__ __forceinline__ int64_t query_off(const QueryBatch& qb, int64_t qi) {
 }
 
 hipError_t launch_index_query(const IndexView& ix, const QueryBatch& qb, hipStream_t s);
-// persistent form: `blocks` blocks of 4 waves; the batch size is read from
-// q_count (device); `counter` (device) is reset by a kernel in the same stream
+// Device-counted forms: `blocks` blocks of 4 waves; the batch size is read
+// from q_count (device).  looping = false: one wave per query, blocks*4 must
+// cover every batch size the call may see.  looping = true: waves take
+// further queries from `counter` (device), reset by a kernel in the same stream.
 hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
-                                         unsigned long long* counter, int blocks, hipStream_t s);
+                                         unsigned long long* counter, int blocks, bool looping, hipStream_t s);
 
 // Full scan.  `part` must hold scan_partial_entries(...) keys.
 struct ScanPlan {

@@ -38,7 +38,7 @@ namespace lcpx {
 constexpr int kQueryWaves = 4;
 constexpr int kTieUnroll = 8;
 constexpr int kFewTied = 16;  // tied selections of at most this many ids use repeated wave minima
-constexpr int kSelMax = kAdjWindow / 4;  // selected blocks the pruned tie scan keeps in the LDS window
+constexpr int kSelMax = kAdjWindow / 4;  // 32-bit entries of the LDS window the tie selections reuse
 
 // A[j] for the 64 positions j = j0 + dir * lane: from the wave's LDS window
 // when the whole chunk lies inside it, else from global memory.  Lanes whose
@@ -52,6 +52,163 @@ __device__ __forceinline__ int a_lane(const uint8_t* __restrict__ A, const uint8
     const bool in_win = jmin >= wbase && jmax < wbase + kAdjWindow;
     if (j < lo_ok || j > hi_ok) return -1;
     return in_win ? (int)win[j - wbase] : (int)A[j];
+}
+
+// Inner group G_{c+1} = [in_lo, in_hi) around p, fewer than 128 rows, in rank
+// order.  The LCP of T[p+t] is the prefix minimum of lR, A[p+1..p+t]; that of
+// T[p-1-t] the prefix minimum of lL, A[p-1..p-t].  Keys (255 - LCP) << 32 | id
+// are held in registers (two chunks of 64 per side) until the last A read,
+// then compacted into the wave's LDS window; each key's rank is the number of
+// keys below it.
+__device__ __forceinline__ void inner_by_rank(const IndexView& ix, uint8_t* win, int64_t wbase, int64_t p,
+                                              int64_t in_lo, int64_t in_hi, int lL, int lR, int n_gt,
+                                              int32_t* __restrict__ oid, int32_t* __restrict__ olc) {
+    const int lane = lane_id();
+    const int64_t nr = in_hi - p;
+    const int64_t nl = p - in_lo;
+    uint32_t id[2][2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {  // all perm loads in flight first
+            const int64_t t = b * kWave + lane;
+            const bool act = t < (sd == 0 ? nr : nl);
+            id[sd][b] = act ? (uint32_t)ix.perm[sd == 0 ? p + t : p - 1 - t] : 0u;
+        }
+    uint64_t key[2][2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+        const int64_t n = sd == 0 ? nr : nl;
+        int carry = 255;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t t = b * kWave + lane;
+            key[sd][b] = kKeyMax;
+            if (b * kWave < n) {
+                // right: row p+t needs A[p+t]; left: row p-1-t needs A[p-t]
+                const int av = sd == 0 ? a_lane(ix.A, win, wbase, p + b * kWave, +1, p + 1, in_hi - 1)
+                                       : a_lane(ix.A, win, wbase, p - b * kWave, -1, in_lo + 1, p - 1);
+                const int a = t < n ? (t == 0 ? (sd == 0 ? lR : lL) : av) : 255;
+                int v = wave_prefix_min(a);
+                v = v < carry ? v : carry;
+                carry = readlane_i(v, kWave - 1);
+                if (t < n) key[sd][b] = rank_key(v, id[sd][b]);
+            }
+        }
+    }
+    uint64_t* s64 = reinterpret_cast<uint64_t*>(win);  // the A window is not read again
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t t = b * kWave + lane;
+            if (t < (sd == 0 ? nr : nl)) s64[sd == 0 ? t : nr + t] = key[sd][b];
+        }
+    const int n2 = (n_gt + 1) & ~1;
+    if (lane == 0 && n_gt < n2) s64[n_gt] = kKeyMax;  // pad to whole 16-byte reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int rank[2][2] = {{0, 0}, {0, 0}};
+    const uint4* s4 = reinterpret_cast<const uint4*>(win);
+#pragma unroll 2
+    for (int j = 0; j < n2 / 2; ++j) {
+        const uint4 x = s4[j];
+        const uint64_t k0 = ((uint64_t)x.y << 32) | x.x;
+        const uint64_t k1 = ((uint64_t)x.w << 32) | x.z;
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) rank[sd][b] += (k0 < key[sd][b]) + (k1 < key[sd][b]);
+    }
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+            if (key[sd][b] != kKeyMax) {
+                oid[rank[sd][b]] = key_id(key[sd][b]);
+                olc[rank[sd][b]] = key_lcp(key[sd][b]);
+            }
+}
+
+// The m lowest ids among at most kTieUnroll*64 tied positions [l, in_lo) and
+// [in_hi, r), 16 < m <= kSelMax: every id in registers; the m-th smallest, tau,
+// by bisection on the id bits from the most significant (the ids are
+// distinct, so exactly m of them are <= tau); those m are compacted into the
+// wave's LDS window and each is written at its rank, the count of selected
+// ids below it.
+__device__ __forceinline__ void tied_select(const IndexView& ix, int64_t l, int64_t in_lo, int64_t in_hi, int64_t r,
+                                            int m, int c, int32_t* __restrict__ oid, int32_t* __restrict__ olc,
+                                            uint32_t* sel) {
+    const int lane = lane_id();
+    const int64_t nleft = in_lo - l;
+    const int64_t tn = nleft + (r - in_hi);
+    uint32_t id[kTieUnroll];
+#pragma unroll
+    for (int u = 0; u < kTieUnroll; ++u) {
+        const int64_t t = u * kWave + lane;
+        const int64_t j = t < nleft ? l + t : in_hi + (t - nleft);
+        id[u] = t < tn ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;  // above every id: never selected
+    }
+    const int bits = 32 - __builtin_clz((uint32_t)(ix.N - 1) | 1u);  // ids are < 2^bits
+    uint32_t pre = 0;  // the bits of tau above bit b
+    int rem = m;       // rank of tau among the ids that share those bits
+#pragma unroll 1
+    for (int b = bits - 1; b >= 0; --b) {
+        const uint32_t want = pre << 1;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kTieUnroll; ++u) cnt += popc64(ballot((id[u] >> b) == want));
+        if (rem <= cnt) {
+            pre = want;
+        } else {
+            rem -= cnt;
+            pre = want | 1u;
+        }
+    }
+    const uint32_t tau = pre;
+    int n = 0;
+#pragma unroll
+    for (int u = 0; u < kTieUnroll; ++u) {
+        const bool s = id[u] <= tau;
+        const uint64_t bal = ballot(s);
+        const int pos = n + count_below(bal);
+        if (s && pos < kSelMax) sel[pos] = id[u];
+        n += popc64(bal);
+    }
+    const int m4 = (m + 3) & ~3;
+    if (m + lane < m4) sel[m + lane] = 0xFFFFFFFFu;  // pad to whole 16-byte reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    constexpr int kPer = kSelMax / kWave;  // selected ids per lane
+    uint32_t v[kPer];
+    int rank[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = t * kWave + lane;
+        v[t] = e < m ? sel[e] : 0u;
+        rank[t] = 0;
+    }
+    const uint4* s4 = reinterpret_cast<const uint4*>(sel);
+#pragma unroll 2
+    for (int j = 0; j < m4 / 4; ++j) {
+        const uint4 x = s4[j];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t)
+            rank[t] += (x.x < v[t]) + (x.y < v[t]) + (x.z < v[t]) + (x.w < v[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+        const int e = t * kWave + lane;
+        if (e < m) {
+            oid[rank[t]] = (int32_t)v[t];
+            olc[rank[t]] = c;
+        }
+    }
 }
 
 // The m lowest ids among the tied positions [l, in_lo) and [in_hi, r) using
@@ -177,7 +334,7 @@ __device__ __forceinline__ void tied_pruned(const IndexView& ix, int64_t l, int6
 
 template <int NR, int VEC>
 __device__ __forceinline__ void index_query_body(const IndexView& ix, const QueryBatch& qb, int64_t qi) {
-    extern __shared__ uint32_t s_dyn[];  // [kQueryWaves][W] query words, then [kQueryWaves][kAdjWindow] A bytes
+    extern __shared__ __align__(16) uint32_t s_dyn[];  // [kQueryWaves][W] query words, then [kQueryWaves][kAdjWindow] A bytes
     const RowGeo g = ix.g;
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -332,7 +489,12 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     const int m = kp - n_gt;
 
     // ---- 3. inner group G_{c+1}, ranked by (LCP desc, id asc)
-    if (n_gt > 0) {
+    if constexpr (NR <= 2) {
+        // at most 127 rows (k <= 128): all keys in registers while A is read,
+        // then into the LDS window, each written at its rank (the count of
+        // keys below it; keys are distinct since ids are)
+        if (n_gt > 0) inner_by_rank(ix, win, wbase, p, in_lo, in_hi, lL, lR, n_gt, oid, olc);
+    } else if (n_gt > 0) {
         WaveList<NR> inner;
         inner.init();
         int carry = 255;
@@ -417,6 +579,8 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 oid[n_gt + lane] = (int32_t)mine;
                 olc[n_gt + lane] = c;
             }
+        } else if (m <= kSelMax && (r - l) - n_gt <= kTieUnroll * kWave) {
+            tied_select(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else if (m <= kSelMax && (in_lo - l) + (r - in_hi) >= (int64_t)kWave * 4 * (m > 8 ? m : 8)) {
             tied_pruned<NR>(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else {
@@ -472,17 +636,24 @@ __device__ __forceinline__ void one_query_per_wave(const IndexView& ix, const Qu
 // query from a device counter (reset to 0 before the launch) until the batch
 // size read from device memory is reached.  Queries of uneven cost balance
 // themselves; the order in which waves take them never reaches the output.
+// Persistent form: wave w of the grid first answers query w, then (only when
+// the grid has fewer waves than the batch has queries) takes further queries
+// nwaves, nwaves + 1, ... from the device work counter.  A grid of one wave
+// per query of the capacity therefore needs no atomics at all.
 template <int NR, int VEC>
 __device__ __forceinline__ void queries_from_counter(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
                                                      unsigned long long* counter) {
     const int64_t Q = *q_count;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t nwaves = (int64_t)gridDim.x * kQueryWaves;
+    int64_t qi = (int64_t)blockIdx.x * kQueryWaves + wv;
 #pragma unroll 1
-    for (;;) {
+    while (qi < Q) {
+        index_query_body<NR, VEC>(ix, qb, qi);
+        if (nwaves >= Q) break;
         unsigned long long got = 0;
         if (lane_id() == 0) got = atomicAdd(counter, 1ull);
-        const int64_t qi = (int64_t)readlane64(got, 0);
-        if (qi >= Q) break;
-        index_query_body<NR, VEC>(ix, qb, qi);
+        qi = nwaves + (int64_t)readlane64(got, 0);
     }
 }
 
@@ -501,6 +672,24 @@ template <int NR, int VEC>
 __global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_index_query_persistent(
     IndexView ix, QueryBatch qb, const int64_t* q_count, unsigned long long* counter) {
     queries_from_counter<NR, VEC>(ix, qb, q_count, counter);
+}
+
+// One wave per query of the capacity; waves past the device-side batch size
+// leave at once.
+template <int NR, int VEC>
+__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_index_query_counted(
+    IndexView ix, QueryBatch qb, const int64_t* q_count) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t qi = (int64_t)blockIdx.x * kQueryWaves + wv;
+    if (qi < *q_count) index_query_body<NR, VEC>(ix, qb, qi);
+}
+
+template <int VEC>
+__global__ __launch_bounds__(kQueryWaves * kWave) void k_index_query_counted_wide(IndexView ix, QueryBatch qb,
+                                                                                 const int64_t* q_count) {
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t qi = (int64_t)blockIdx.x * kQueryWaves + wv;
+    if (qi < *q_count) index_query_body<16, VEC>(ix, qb, qi);
 }
 
 template <int VEC>
@@ -539,34 +728,48 @@ static hipError_t launch_nr(const IndexView& ix, const QueryBatch& qb, hipStream
 
 template <int NR>
 static hipError_t launch_persistent_nr(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
-                                       unsigned long long* counter, int blocks, hipStream_t s) {
+                                       unsigned long long* counter, int blocks, bool looping, hipStream_t s) {
     const size_t shm = (size_t)kQueryWaves * (ix.g.W * sizeof(uint32_t) + kAdjWindow);
     const dim3 blk(kQueryWaves * kWave);
+    const dim3 grid((unsigned)blocks);
+    const int vec = ix.g.W % 4 == 0 ? 4 : ix.g.W % 2 == 0 ? 2 : 1;
+    if (!looping) {
+        if constexpr (NR == 16) {
+            if (vec == 4) hipLaunchKernelGGL((k_index_query_counted_wide<4>), grid, blk, shm, s, ix, qb, q_count);
+            else if (vec == 2) hipLaunchKernelGGL((k_index_query_counted_wide<2>), grid, blk, shm, s, ix, qb, q_count);
+            else hipLaunchKernelGGL((k_index_query_counted_wide<1>), grid, blk, shm, s, ix, qb, q_count);
+        } else {
+            if (vec == 4) hipLaunchKernelGGL((k_index_query_counted<NR, 4>), grid, blk, shm, s, ix, qb, q_count);
+            else if (vec == 2) hipLaunchKernelGGL((k_index_query_counted<NR, 2>), grid, blk, shm, s, ix, qb, q_count);
+            else hipLaunchKernelGGL((k_index_query_counted<NR, 1>), grid, blk, shm, s, ix, qb, q_count);
+        }
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
     if constexpr (NR == 16) {
-        if (ix.g.W % 4 == 0)
-            hipLaunchKernelGGL((k_index_query_persistent_wide<4>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
-        else if (ix.g.W % 2 == 0)
-            hipLaunchKernelGGL((k_index_query_persistent_wide<2>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+        if (vec == 4)
+            hipLaunchKernelGGL((k_index_query_persistent_wide<4>), grid, blk, shm, s, ix, qb, q_count, counter);
+        else if (vec == 2)
+            hipLaunchKernelGGL((k_index_query_persistent_wide<2>), grid, blk, shm, s, ix, qb, q_count, counter);
         else
-            hipLaunchKernelGGL((k_index_query_persistent_wide<1>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+            hipLaunchKernelGGL((k_index_query_persistent_wide<1>), grid, blk, shm, s, ix, qb, q_count, counter);
     } else {
-        if (ix.g.W % 4 == 0)
-            hipLaunchKernelGGL((k_index_query_persistent<NR, 4>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
-        else if (ix.g.W % 2 == 0)
-            hipLaunchKernelGGL((k_index_query_persistent<NR, 2>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+        if (vec == 4)
+            hipLaunchKernelGGL((k_index_query_persistent<NR, 4>), grid, blk, shm, s, ix, qb, q_count, counter);
+        else if (vec == 2)
+            hipLaunchKernelGGL((k_index_query_persistent<NR, 2>), grid, blk, shm, s, ix, qb, q_count, counter);
         else
-            hipLaunchKernelGGL((k_index_query_persistent<NR, 1>), dim3(blocks), blk, shm, s, ix, qb, q_count, counter);
+            hipLaunchKernelGGL((k_index_query_persistent<NR, 1>), grid, blk, shm, s, ix, qb, q_count, counter);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& qb, const int64_t* q_count,
-                                         unsigned long long* counter, int blocks, hipStream_t s) {
-    if (qb.k_max <= 64) return launch_persistent_nr<1>(ix, qb, q_count, counter, blocks, s);
-    if (qb.k_max <= 128) return launch_persistent_nr<2>(ix, qb, q_count, counter, blocks, s);
-    if (qb.k_max <= 256) return launch_persistent_nr<4>(ix, qb, q_count, counter, blocks, s);
-    return launch_persistent_nr<16>(ix, qb, q_count, counter, blocks, s);
+                                         unsigned long long* counter, int blocks, bool looping, hipStream_t s) {
+    if (qb.k_max <= 64) return launch_persistent_nr<1>(ix, qb, q_count, counter, blocks, looping, s);
+    if (qb.k_max <= 128) return launch_persistent_nr<2>(ix, qb, q_count, counter, blocks, looping, s);
+    if (qb.k_max <= 256) return launch_persistent_nr<4>(ix, qb, q_count, counter, blocks, looping, s);
+    return launch_persistent_nr<16>(ix, qb, q_count, counter, blocks, looping, s);
 }
 
 hipError_t launch_index_query(const IndexView& ix, const QueryBatch& qb, hipStream_t s) {

@@ -55,6 +55,13 @@ def test_error_paths_without_gpu():
     lib.lcp_topk.restype = ctypes.c_int
     lib.lcp_topk.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
     assert lib.lcp_topk(None, None, 1, None, None, None, None) == -1
+    lib.lcp_topk_persistent.restype = ctypes.c_int
+    lib.lcp_topk_persistent.argtypes = ([ctypes.c_void_p] * 2 + [ctypes.c_int64] + [ctypes.c_void_p] * 3 +
+                                        [ctypes.c_int32] + [ctypes.c_void_p] * 2 + [ctypes.c_int32, ctypes.c_void_p])
+    assert lib.lcp_topk_persistent(None, None, 8, None, None, None, 10, None, None, 0, None) == -1
+    lib.lcp_index_append.restype = ctypes.c_int
+    lib.lcp_index_append.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    assert lib.lcp_index_append(None, None, 1, None) == -1
     lib.lcp_index_free(None)
 
 

@@ -278,11 +278,12 @@ def test_long_tied_blocks(P):
         kd = torch.from_numpy(w.k).cuda()
         od = torch.from_numpy(ref.offsets).cuda()
         cnt = torch.tensor([w.Q], dtype=torch.int64, device="cuda")
-        ids = torch.full_like(ref.ids, -9)
-        lcps = torch.full_like(ref.lcps, -9)
-        idx.topk_persistent(qd, cnt, kd, od, int(w.k.max()), ids, lcps)
-        torch.cuda.synchronize()
-        assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps)
+        for blocks in (0, 8):  # one wave per query; 32 looping waves
+            ids = torch.full_like(ref.ids, -9)
+            lcps = torch.full_like(ref.lcps, -9)
+            idx.topk_persistent(qd, cnt, kd, od, int(w.k.max()), ids, lcps, blocks=blocks)
+            torch.cuda.synchronize()
+            assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps), blocks
 
 
 def test_served_results_equal_alone(P):
@@ -392,15 +393,22 @@ def test_captured_persistent_launch_replays(P):
         ref = idx.topk(qd, w.k)
         torch.cuda.synchronize()
         ref_ids, ref_lcp = ref.ids.cpu().numpy(), ref.lcps.cpu().numpy()
-        cl = batching.CapturedLaunch(idx, cap_queries=3000, k_max=100)
-        for n in (3000, 1000, 1, 0, 2999, 3000):
-            ids, lcps, off = cl.run(qd[:n], w.k[:n])
+        for blocks in (0, 16):  # one wave per query; a 64-wave grid whose waves loop
+            cl = batching.CapturedLaunch(idx, cap_queries=3000, k_max=100, blocks=blocks)
+            for n in (3000, 1000, 1, 0, 2999, 3000):
+                ids, lcps, off = cl.run(qd[:n], w.k[:n])
+                torch.cuda.synchronize()
+                gi, gl = ids.cpu().numpy(), lcps.cpu().numpy()
+                assert gi.shape[0] == int(w.k[:n].sum())
+                assert (gi == ref_ids[: gi.shape[0]]).all() and (gl == ref_lcp[: gl.shape[0]]).all(), (blocks, n)
+                idx.topk(qd[:7], 3)  # eager work between replays
+                torch.cuda.synchronize()
+            # back-to-back replays without a host sync in between (alternating staging buffers)
+            outs = [tuple(t.clone() for t in cl.run(qd[:m], w.k[:m])[:2]) for m in (2000, 3000, 500)]
             torch.cuda.synchronize()
-            gi, gl = ids.cpu().numpy(), lcps.cpu().numpy()
-            assert gi.shape[0] == int(w.k[:n].sum())
-            assert (gi == ref_ids[: gi.shape[0]]).all() and (gl == ref_lcp[: gl.shape[0]]).all(), n
-            idx.topk(qd[:7], 3)  # eager work between replays
-            torch.cuda.synchronize()
+            for (gi, gl), m in zip(outs, (2000, 3000, 500)):
+                tot = int(w.k[:m].sum())
+                assert (gi.cpu().numpy() == ref_ids[:tot]).all() and (gl.cpu().numpy() == ref_lcp[:tot]).all()
         sample = np.arange(0, 3000, 97)
         wi, wl, woff = oracle.c_topk(w.db, w.queries[sample], w.k[sample])
         for j, qi in enumerate(sample):
