@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU baseline sample")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="duration of each fixed-rate serving run (0 disables)")
-    ap.add_argument("--serve-rates", type=str, default="10000,100000")
+    ap.add_argument("--serve-rates", type=str, default="1000,10000,100000")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the uneven-k batch comparison")
     ap.add_argument("--sensor-steps", type=int, default=5000,

@@ -134,25 +134,15 @@ __device__ __forceinline__ void inner_by_rank(const IndexView& ix, uint8_t* win,
             }
 }
 
-// The m lowest ids among at most kTieUnroll*64 tied positions [l, in_lo) and
-// [in_hi, r), 16 < m <= kSelMax: every id in registers; the m-th smallest, tau,
-// by bisection on the id bits from the most significant (the ids are
-// distinct, so exactly m of them are <= tau); those m are compacted into the
-// wave's LDS window and each is written at its rank, the count of selected
-// ids below it.
-__device__ __forceinline__ void tied_select(const IndexView& ix, int64_t l, int64_t in_lo, int64_t in_hi, int64_t r,
-                                            int m, int c, int32_t* __restrict__ oid, int32_t* __restrict__ olc,
-                                            uint32_t* sel) {
+// The m lowest ids among at most kTieUnroll*64 tied positions, 16 < m <=
+// kSelMax, whose ids the caller holds in `id` (0xFFFFFFFF past the range
+// end): the m-th smallest, tau, by bisection on the id bits from the most
+// significant (the ids are distinct, so exactly m of them are <= tau); those
+// m are compacted into the wave's LDS window and each is written at its rank,
+// the count of selected ids below it.
+__device__ __forceinline__ void tied_select(const IndexView& ix, const uint32_t* id, int m, int c,
+                                            int32_t* __restrict__ oid, int32_t* __restrict__ olc, uint32_t* sel) {
     const int lane = lane_id();
-    const int64_t nleft = in_lo - l;
-    const int64_t tn = nleft + (r - in_hi);
-    uint32_t id[kTieUnroll];
-#pragma unroll
-    for (int u = 0; u < kTieUnroll; ++u) {
-        const int64_t t = u * kWave + lane;
-        const int64_t j = t < nleft ? l + t : in_hi + (t - nleft);
-        id[u] = t < tn ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;  // above every id: never selected
-    }
     const int bits = 32 - __builtin_clz((uint32_t)(ix.N - 1) | 1u);  // ids are < 2^bits
     uint32_t pre = 0;  // the bits of tau above bit b
     int rem = m;       // rank of tau among the ids that share those bits
@@ -488,6 +478,19 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     const int n_gt = (int)(in_hi - in_lo);
     const int m = kp - n_gt;
 
+    // ids of a short tied range are requested now, so that their round trip
+    // overlaps the inner group's
+    const int64_t tnl = in_lo - l;
+    const int64_t tn = tnl + (r - in_hi);
+    const bool held = m > 0 && c > 0 && m <= kSelMax && tn <= kTieUnroll * kWave;
+    uint32_t tid[kTieUnroll];
+#pragma unroll
+    for (int u = 0; u < kTieUnroll; ++u) {
+        const int64_t t = u * kWave + lane;
+        const int64_t j = t < tnl ? l + t : in_hi + (t - tnl);
+        tid[u] = held && t < tn ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;  // above every id
+    }
+
     // ---- 3. inner group G_{c+1}, ranked by (LCP desc, id asc)
     if constexpr (NR <= 2) {
         // at most 127 rows (k <= 128): all keys in registers while A is read,
@@ -553,18 +556,10 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 }
                 got += popc64(bal);
             }
-        } else if (m <= kFewTied && (r - l) - n_gt <= kTieUnroll * kWave) {
+        } else if (held && m <= kFewTied) {
             // small case: every tied id in registers, then m rounds of "take the
             // wave minimum and remove it"
-            const int64_t nleft = in_lo - l;
-            const int64_t tn = nleft + (r - in_hi);
-            uint32_t id[kTieUnroll];
-#pragma unroll
-            for (int u = 0; u < kTieUnroll; ++u) {
-                const int64_t t = u * kWave + lane;
-                const int64_t j = t < nleft ? l + t : in_hi + (t - nleft);
-                id[u] = t < tn ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;
-            }
+            uint32_t* id = tid;
             uint32_t mine = 0xFFFFFFFFu;  // lane e keeps the e-th smallest
             for (int e = 0; e < m; ++e) {
                 uint32_t v = id[0];
@@ -579,8 +574,8 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 oid[n_gt + lane] = (int32_t)mine;
                 olc[n_gt + lane] = c;
             }
-        } else if (m <= kSelMax && (r - l) - n_gt <= kTieUnroll * kWave) {
-            tied_select(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
+        } else if (held) {
+            tied_select(ix, tid, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else if (m <= kSelMax && (in_lo - l) + (r - in_hi) >= (int64_t)kWave * 4 * (m > 8 ? m : 8)) {
             tied_pruned<NR>(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else {

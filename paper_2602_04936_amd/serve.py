@@ -123,14 +123,22 @@ class GpuExecutor:
             }
             self.slots.append(s)
 
-    def warmup(self, sample: np.ndarray, k: int = 1):
-        """One small launch per slot before timing starts (first use of a
-        stream allocates its per-stream scratch)."""
-        for s in self.slots:
-            self.launch(s, [Request(-1, 0.0, sample[:1], k)])
-        self.torch.cuda.synchronize()
-        for s in self.slots:
-            s["batch"] = None
+    def warmup(self, sample: np.ndarray, ks=(1,), max_batch: int = 1):
+        """Launches on every slot before timing starts, one per k in `ks` and
+        one of `max_batch` queries: the first use of a stream allocates its
+        per-stream scratch, and the first launch of each kernel variant (they
+        differ by the batch's largest k) loads it."""
+        mb = max(1, int(max_batch))  # within the slots' capacity
+        sizes = sorted({min(b, mb) for b in (1, 9, 17, mb)})  # the scan's queries per wave change at 9 and 17
+        for k in ks:
+            for b in sizes:
+                reps = -(-b // sample.shape[0])
+                rows = np.concatenate([sample] * reps, axis=0)[:b]
+                for s in self.slots:
+                    self.launch(s, [Request(-1, 0.0, rows, int(k))])
+                self.torch.cuda.synchronize()
+                for s in self.slots:
+                    s["batch"] = None
 
     def free_slot(self):
         for s in self.slots:
@@ -254,6 +262,31 @@ def requests_from_schedule(query_pool: np.ndarray, arrival_s, batch_sizes, ks) -
     return reqs
 
 
+def _variant_ks(requests) -> List[int]:
+    """The largest k of each kernel variant the requests use (the per-query
+    list grows at k = 65, 129 and 257; a launch with the largest k of a
+    variant also sizes per-stream scratch for every smaller one)."""
+    best = {}
+    for r in requests:
+        v = 0 if r.k <= 64 else 1 if r.k <= 128 else 2 if r.k <= 256 else 3
+        best[v] = max(best.get(v, 1), int(r.k))
+    return [best[v] for v in sorted(best)]
+
+
+def _without_gc(fn):
+    """Run fn with Python's cyclic garbage collector paused (a collection in
+    the middle of a timed loop shows up as a latency spike)."""
+    import gc
+    was = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        return fn()
+    finally:
+        if was:
+            gc.enable()
+
+
 def run_served(index, requests: List[Request], n_slots: int = 3, budget_bytes: int = 1 << 30,
                cap_queries: int = 8192, scan: bool = False) -> dict:
     """Continuous batching over `n_slots` streams under a device-memory budget;
@@ -265,10 +298,11 @@ def run_served(index, requests: List[Request], n_slots: int = 3, budget_bytes: i
     ce = min(ce, cq * kmax)
     ex = GpuExecutor(index, n_slots, cq, ce, scan=scan)
     if requests:
-        ex.warmup(requests[0].queries)
+        bmax = min(max(r.b for r in requests), cq, ce // max(kmax, 1))
+        ex.warmup(requests[0].queries, ks=_variant_ks(requests), max_batch=bmax)
     sched = Scheduler(cq, ce)
     duration = max((r.arrival for r in requests), default=0.0)
-    done = run_loop(requests, sched, ex)
+    done = _without_gc(lambda: run_loop(requests, sched, ex))
     rep = latency_report(done, duration)
     rep["slots"] = n_slots
     rep["path"] = "scan" if scan else "index"
@@ -284,21 +318,30 @@ def run_synchronous(index, requests: List[Request], scan: bool = True, max_wall_
     clock = lambda: time.perf_counter() - t0  # noqa: E731
     done = []
     fn = index.scan_topk if scan else index.topk
-    if requests:  # first call on the stream allocates its scratch
-        fn(requests[0].queries[:1], 1)
+    if requests:  # the same warm-up as the batched executor gets: every kernel variant and batch shape
+        bmax = max(r.b for r in requests)
+        sample = requests[0].queries
+        for kk in _variant_ks(requests):
+            for b in sorted({1, min(9, bmax), min(17, bmax), bmax}):
+                rows = np.concatenate([sample] * (-(-b // sample.shape[0])), axis=0)[:b]
+                fn(rows, kk)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-    for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
-        while clock() < r.arrival:
-            pass
-        res = fn(r.queries, r.k)
-        torch.cuda.synchronize()
-        r.ids = res.ids.cpu().numpy().reshape(r.b, r.k)
-        r.lcps = res.lcps.cpu().numpy().reshape(r.b, r.k)
-        r.done = clock()
-        done.append(r)
-        if clock() > max_wall_s:
-            break
+
+    def loop():
+        for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
+            while clock() < r.arrival:
+                pass
+            res = fn(r.queries, r.k)
+            torch.cuda.synchronize()
+            r.ids = res.ids.cpu().numpy().reshape(r.b, r.k)
+            r.lcps = res.lcps.cpu().numpy().reshape(r.b, r.k)
+            r.done = clock()
+            done.append(r)
+            if clock() > max_wall_s:
+                break
+
+    loop()
     duration = max((r.arrival for r in requests), default=0.0)
     rep = latency_report(done, duration)
     rep["path"] = "scan" if scan else "index"
