@@ -286,6 +286,42 @@ def test_long_tied_blocks(P):
             assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps), blocks
 
 
+def _tie_case(rng, T, n_gt, n_other=300, L=6):
+    """Rows for query 1 5 5 5 5 5 with exactly n_gt rows of LCP >= 2 (LCPs 2..6
+    mixed), T rows of LCP exactly 1 and n_other of LCP 0, ids shuffled."""
+    q = np.array([1, 5, 5, 5, 5, 5], np.uint8)[:L]
+    inner = np.tile(q, (n_gt, 1))
+    for i in range(n_gt):  # break the match at a random position >= 2 (or never)
+        d = int(rng.integers(2, L + 1))
+        if d < L:
+            inner[i, d] = rng.choice([0, 2, 3, 4, 6, 7])
+            inner[i, d + 1:] = rng.integers(0, 8, L - d - 1)
+    tied = rng.integers(0, 8, (T, L)).astype(np.uint8)
+    tied[:, 0] = 1
+    tied[:, 1] = rng.choice(np.array([0, 2, 3, 4, 6, 7], np.uint8), T)
+    other = rng.integers(0, 8, (n_other, L)).astype(np.uint8)
+    other[:, 0] = rng.choice(np.array([0, 2, 3], np.uint8), n_other)
+    db = np.concatenate([inner, tied, other])
+    return db[rng.permutation(db.shape[0])], q[None, :]
+
+
+@pytest.mark.parametrize("T,n_gt,k", [
+    (512, 0, 16), (512, 0, 17), (512, 3, 259), (513, 0, 17), (512, 0, 257), (64, 0, 64),
+    (3000, 2, 12), (20000, 5, 200), (60000, 5, 200), (200, 127, 128), (200, 63, 64), (200, 64, 66),
+    (511, 120, 128)])
+def test_tie_selection_boundaries(P, T, n_gt, k):
+    """Each tie-selection path at its limits: wave minima (m <= 16, <= 512
+    tied rows), bisection select (m <= 256, <= 512 rows), pruned by block
+    minima (long ranges), the sorted list otherwise; inner groups of up to
+    127 rows ranked by counting."""
+    rng = np.random.default_rng(T * 1000 + n_gt * 7 + k)
+    db, q = _tie_case(rng, T, n_gt)
+    c, above, tn = _tie_shape(db, q[0], k)
+    assert c == 1 and above == n_gt and tn == T, (c, above, tn)
+    qs = np.repeat(q, 4, axis=0)
+    check_against_oracle(P, db, qs, [k, 1, k, max(1, k - 1)], 8, f"ties T={T} n_gt={n_gt} k={k}")
+
+
 def test_served_results_equal_alone(P):
     """Continuous batching on the GPU: every request's answer equals the
     oracle's answer for that request alone."""
