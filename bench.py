@@ -316,9 +316,10 @@ def main():
             iw = meter.idle_watts(es)
             energy = {"idle_watts": round(iw, 1) if iw is not None else None}
 
-            def run_index():
-                idx.topk(q_dev, ks, out=(ids, lcps))
-                return w.Q
+            def run_index():  # the timed steps' configuration: round-robin over the streams
+                for j in range(nstreams):
+                    idx.topk(q_dev, ks, out=outs[j], stream=streams[j])
+                return w.Q * nstreams
 
             def run_scan(ix):
                 def f():
@@ -326,7 +327,7 @@ def main():
                     return w.Q
                 return f
 
-            energy["index"] = meter.measure(run_index, es, sync_every=16)
+            energy["index"] = meter.measure(run_index, es, sync_every=64)
             energy["full_scan"] = meter.measure(run_scan(idx), es, sync_every=1)
             sweep = {"1": energy["full_scan"].get("j_per_query")}
             for B in (4, 16, 64, 256):
