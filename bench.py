@@ -106,11 +106,11 @@ def main():
     def timed_steps(n_str):
         for _ in range(args.warmup):
             for j in range(n_str):
-                idx.topk(q_dev, ks, out=outs[j], stream=streams[j])
+                idx.topk(q_dev, args.k, out=outs[j], stream=streams[j])
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(args.steps):
-            idx.topk(q_dev, ks, out=outs[i % n_str], stream=streams[i % n_str])
+            idx.topk(q_dev, args.k, out=outs[i % n_str], stream=streams[i % n_str])
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
@@ -318,7 +318,7 @@ def main():
 
             def run_index():  # the timed steps' configuration: round-robin over the streams
                 for j in range(nstreams):
-                    idx.topk(q_dev, ks, out=outs[j], stream=streams[j])
+                    idx.topk(q_dev, args.k, out=outs[j], stream=streams[j])
                 return w.Q * nstreams
 
             def run_scan(ix):

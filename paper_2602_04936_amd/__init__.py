@@ -126,6 +126,7 @@ class Index:
         h = ctypes.c_void_p()
         _check(lib.lcp_index_build(t.data_ptr(), N, L, int(V), _stream_handle(stream), ctypes.byref(h)))
         self._h = h
+        self._kcache = {}
         n, l, v, tb, w = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib.lcp_index_info(h, ctypes.byref(n), ctypes.byref(l), ctypes.byref(v), ctypes.byref(tb),
                                   ctypes.byref(w)))
@@ -140,6 +141,20 @@ class Index:
         if q.shape[1] != self.L:
             raise ValueError(f"queries have L={q.shape[1]}, index has L={self.L}")
         Q = q.shape[0]
+        if isinstance(k, (int, np.integer)):
+            # one k for every query: the k and offset arrays are built once per
+            # (Q, k) and reused (read-only), keeping the per-call host work small
+            key = (Q, int(k))
+            hit = self._kcache.get(key)
+            if hit is None:
+                kk = np.full(Q, int(k), dtype=np.int32)
+                off = np.arange(Q + 1, dtype=np.int64) * int(k)
+                kk.flags.writeable = False
+                off.flags.writeable = False
+                if len(self._kcache) >= 64:
+                    self._kcache.clear()
+                hit = self._kcache[key] = (kk, off)
+            return (q,) + hit
         kk = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (Q,)))
         off = np.zeros(Q + 1, dtype=np.int64)
         np.cumsum(kk, out=off[1:])

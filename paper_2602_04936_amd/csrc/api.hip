@@ -283,15 +283,21 @@ lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int6
     StreamCtx* c = nullptr;
     st = get_ctx(idx, s, &c);
     if (st != LCP_OK) return st;
-    int32_t kmax = 1;
-    bool uniform = true;
+    // branch-free pass (vectorised): range and uniformity of k
+    const int32_t k0 = k[0];
+    int32_t kmin = k0, kmax = k0, diff = 0;
     for (int64_t i = 0; i < Q; ++i) {
-        if (k[i] < 1 || k[i] > LCP_K_MAX)
-            return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
-        kmax = std::max(kmax, k[i]);
-        uniform = uniform && k[i] == k[0];
+        const int32_t v = k[i];
+        kmin = v < kmin ? v : kmin;
+        kmax = v > kmax ? v : kmax;
+        diff |= v ^ k0;
     }
-    if (uniform)  // offsets are i * k: nothing to copy
+    if (kmin < 1 || kmax > LCP_K_MAX) {
+        for (int64_t i = 0; i < Q; ++i)
+            if (k[i] < 1 || k[i] > LCP_K_MAX)
+                return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
+    }
+    if (diff == 0)  // one k for all: offsets are i * k, nothing to copy
         return run_dev(idx, path, queries, Q, nullptr, nullptr, k[0], kmax, out_ids, out_lcp, s, c);
     st = stage_k(c, Q, k);
     if (st != LCP_OK) return st;
