@@ -70,15 +70,19 @@ __device__ __forceinline__ int wave_prefix_min(int v) {
     return v;
 }
 
-// minimum over the wave's lanes (every lane gets it)
+// minimum over the wave's lanes (every lane gets it; call with all lanes
+// active).  Within each row of 16 lanes, DPP lane permutations (swap
+// neighbours, swap pairs, mirror each half, mirror the row) leave every lane
+// with its row's minimum; the four row minima are then read as scalars.
+__device__ __forceinline__ uint32_t dpp_min_step(uint32_t v, uint32_t o) { return o < v ? o : v; }
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const uint32_t o = (uint32_t)__builtin_amdgcn_ds_bpermute((lane ^ d) << 2, (int)v);
-        v = o < v ? o : v;
-    }
-    return v;
+    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+    const uint32_t a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
+    const uint32_t ab = a < b ? a : b, cd = c < d ? c : d;
+    return ab < cd ? ab : cd;
 }
 
 // ---------------------------------------------------------------- rows

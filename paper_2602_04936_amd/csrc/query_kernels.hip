@@ -557,18 +557,36 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 got += popc64(bal);
             }
         } else if (held && m <= kFewTied) {
-            // small case: every tied id in registers, then m rounds of "take the
-            // wave minimum and remove it"
-            uint32_t* id = tid;
+            // small case: each lane sorts its (at most 8) tied ids, then m
+            // rounds take the wave minimum of the lanes' smallest remaining id
+            // and the lane holding it drops that id
+            uint32_t h0 = tid[0], h1 = tid[1], h2 = tid[2], h3 = tid[3], h4 = tid[4], h5 = tid[5], h6 = tid[6],
+                     h7 = tid[7];
+#define LCPX_CE(x, y)                              \
+    {                                              \
+        const uint32_t lo_ = x < y ? x : y;        \
+        y = x < y ? y : x;                         \
+        x = lo_;                                   \
+    }
+            LCPX_CE(h0, h1) LCPX_CE(h2, h3) LCPX_CE(h4, h5) LCPX_CE(h6, h7) LCPX_CE(h0, h2) LCPX_CE(h1, h3)
+            LCPX_CE(h4, h6) LCPX_CE(h5, h7) LCPX_CE(h1, h2) LCPX_CE(h5, h6) LCPX_CE(h0, h4) LCPX_CE(h1, h5)
+            LCPX_CE(h2, h6) LCPX_CE(h3, h7) LCPX_CE(h2, h4) LCPX_CE(h3, h5) LCPX_CE(h1, h2) LCPX_CE(h3, h4)
+            LCPX_CE(h5, h6)
+#undef LCPX_CE
             uint32_t mine = 0xFFFFFFFFu;  // lane e keeps the e-th smallest
             for (int e = 0; e < m; ++e) {
-                uint32_t v = id[0];
-#pragma unroll
-                for (int u = 1; u < kTieUnroll; ++u) v = id[u] < v ? id[u] : v;
-                v = wave_min_u32(v);
+                const uint32_t v = wave_min_u32(h0);
                 if (lane == e) mine = v;
-#pragma unroll
-                for (int u = 0; u < kTieUnroll; ++u) id[u] = id[u] == v ? 0xFFFFFFFFu : id[u];
+                if (h0 == v) {  // one lane: the ids are distinct
+                    h0 = h1;
+                    h1 = h2;
+                    h2 = h3;
+                    h3 = h4;
+                    h4 = h5;
+                    h5 = h6;
+                    h6 = h7;
+                    h7 = 0xFFFFFFFFu;
+                }
             }
             if (lane < m) {
                 oid[n_gt + lane] = (int32_t)mine;
