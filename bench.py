@@ -39,6 +39,8 @@ def parse():
                     help="batch size for the scan-bandwidth measurement (HBM-bound regime)")
     ap.add_argument("--streams", type=int, default=2,
                     help="streams the index-path steps are issued on, round-robin")
+    ap.add_argument("--large-n", type=int, default=8_000_000,
+                    help="rows of the larger-than-Infinity-Cache database (0 skips it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the CPU baseline sample")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -182,6 +184,64 @@ def main():
     plane_bytes = 8
     bw_bytes = w.N * plane_bytes * passes_bw + nbw * row_bytes
     bw_gbs = bw_bytes / (bw_ms / bw_n * 1e-3) / 1e9
+
+    # ---- the same Q=32 pass with the 256 MB Infinity Cache flushed before each
+    # rep (a 512 MiB write between reps), so the plane comes from HBM
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    cold = []
+    for _ in range(10):
+        flush.fill_(1)
+        torch.cuda.synchronize()
+        idx.set_kernel_timing(True)
+        idx.kernel_time(1)
+        idx.scan_topk(qbw, kbw, out=(bw_ids, bw_lcp))
+        c_ms, c_n = idx.kernel_time(1)
+        idx.set_kernel_timing(False)
+        cold.append(c_ms / max(c_n, 1))
+    del flush
+    cold_us = float(np.median(cold)) * 1e3
+    cold_gbs = bw_bytes / (cold_us * 1e-6) / 1e9
+
+    # ---- a database larger than the Infinity Cache: c3's generator at N=8M
+    large = None
+    if args.large_n > 0:
+        wl = synth.c3_like(args.large_n, w.Q, seed=1003, k_fixed=args.k)
+        lidx = P.Index(P.to_device_tokens(wl.db, dev), wl.V)
+        lq = P.to_device_tokens(wl.queries, dev)
+        lo = [(torch.empty(wl.Q * args.k, dtype=torch.int32, device=dev),
+               torch.empty(wl.Q * args.k, dtype=torch.int32, device=dev)) for _ in range(nstreams)]
+        for j in range(nstreams):
+            lidx.topk(lq, args.k, out=lo[j], stream=streams[j])
+        torch.cuda.synchronize()
+        lsteps = max(20, args.steps // 4)
+        t = time.perf_counter()
+        for i in range(lsteps):
+            lidx.topk(lq, args.k, out=lo[i % nstreams], stream=streams[i % nstreams])
+        torch.cuda.synchronize()
+        l_qps = wl.Q * lsteps / (time.perf_counter() - t)
+        lbw = (torch.empty(32 * args.k, dtype=torch.int32, device=dev), torch.empty(32 * args.k, dtype=torch.int32, device=dev))
+        lidx.scan_topk(lq[:32], args.k, out=lbw)
+        torch.cuda.synchronize()
+        lidx.set_kernel_timing(True)
+        lidx.kernel_time(1)
+        for _ in range(10):
+            lidx.scan_topk(lq[:32], args.k, out=lbw)
+        lm, ln = lidx.kernel_time(1)
+        lidx.set_kernel_timing(False)
+        l_pass_us = lm / max(ln, 1) * 1e3
+        t = time.perf_counter()
+        for _ in range(2):
+            lidx.scan_topk(lq, args.k, out=lo[0])
+        torch.cuda.synchronize()
+        l_scan_qps = wl.Q * 2 / (time.perf_counter() - t)
+        large = {"N": wl.N, "db_bytes": int(wl.N * row_bytes),
+                 "index_qps": round(l_qps, 1), "index_ms_per_step": round(wl.Q / l_qps * 1e3, 5),
+                 "scan_qps": round(l_scan_qps, 1),
+                 "scan_pass_q32_us": round(l_pass_us, 2),
+                 "scan_pass_q32_plane_GBps": round(wl.N * plane_bytes / (l_pass_us * 1e-6) / 1e9, 1)}
+        lidx.close()
+        del wl, lq, lo
+        log(args, f"[bench] larger than the Infinity Cache: {large}")
 
     # ---- parity spot check against the CPU oracle (outside every timed region)
     parity = None
@@ -406,12 +466,15 @@ def main():
                  "merge_kernel_ms": round(m_ms / max(m_n, 1), 4), "passes_over_db": passes,
                  "plane_GBps": round(scan_bytes / (scan_kernel_ms * 1e-3) / 1e9, 1),
                  "row_equivalent_GBps": round(w.N * row_bytes * passes / (scan_kernel_ms * 1e-3) / 1e9, 1),
+                 "pair_lcp_per_s": round(w.Q * w.N / (scan_kernel_ms * 1e-3), 1),
                  "paths_bit_identical": paths_agree},
         "scan_roofline": {"kernel": "k_scan", "bound": "hbm", "queries": nbw, "passes_over_db": passes_bw,
                           "achieved": round(bw_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(bw_gbs / HBM_PEAK_GBS, 4),
                           "avg_kernel_us": round(bw_ms / bw_n * 1e3, 2),
-                          "avg_call_us": round(bw_call_us, 2)},
+                          "avg_call_us": round(bw_call_us, 2),
+                          "cold_kernel_us": round(cold_us, 2), "cold_achieved": round(cold_gbs, 1)},
+        "large_db": large,
         "build_ms": round(build_ms, 2),
         "serving": serving,
         "uneven_batch": uneven,
@@ -477,7 +540,16 @@ def cpu_baseline(w, ks, args):
     t = time.perf_counter()
     oracle.c_topk(w.db, w.queries[sel], ks[sel])
     el = time.perf_counter() - t
-    return {"value": round(n / el, 2), "unit": "queries/s", "cores": threads, "kind": "oracle",
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(n / el, 2), "unit": "queries/s", "cores": threads, "kind": "oracle", "cpu": model,
             "sample": f"first {n} of the {w.Q} bench queries against all N={w.N} rows, k={args.k}, "
                       f"C brute force (oracle/cpu_topk.c, OpenMP over queries), {el:.1f} s wall"}
 
