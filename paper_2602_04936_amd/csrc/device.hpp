@@ -54,36 +54,52 @@ __device__ __forceinline__ uint32_t from_lower_lane(uint32_t v) {
 __device__ __forceinline__ uint64_t from_lower_lane64(uint64_t v) {
     return ((uint64_t)from_lower_lane((uint32_t)(v >> 32)) << 32) | from_lower_lane((uint32_t)v);
 }
-__device__ __forceinline__ int from_lane(int v, int src) {
-    return __builtin_amdgcn_ds_bpermute(src << 2, v);
-}
 
-// inclusive prefix minimum over the wave's lanes
+// DPP lane-permutation controls used below (all stay within the wave)
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr3 = 0x113, kDppRowShr4 = 0x114,
+              kDppRowShr8 = 0x118;
+constexpr int kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E;  // quad_perm 1,0,3,2 and 2,3,0,1
+constexpr int kDppRowHalfMirror = 0x141, kDppRowMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+// v combined with the value of another lane chosen by a DPP control; lanes
+// the control or the row/bank masks leave out take `ident`, the operation's
+// identity, so the combining min folds into one DPP instruction
+#define LCPX_DPP(ident, v, ctrl, rmask, bmask) __builtin_amdgcn_update_dpp((ident), (v), (ctrl), (rmask), (bmask), false)
+
+// inclusive prefix minimum over the wave's lanes (call with all lanes
+// active): shifts by 1, 2 and 3 within each row of 16 lanes (from the
+// original values), then by 4 and 8 for the upper banks, then lane 15 of
+// each row into the next row and lane 31 into the upper half
 __device__ __forceinline__ int wave_prefix_min(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int src = lane - d;
-        int o = from_lane(v, src < 0 ? 0 : src);
-        if (src >= 0) v = o < v ? o : v;
-    }
+    constexpr int I = 0x7FFFFFFF;
+    const int x = v;
+    v = min(v, LCPX_DPP(I, x, kDppRowShr1, 0xF, 0xF));
+    v = min(v, LCPX_DPP(I, x, kDppRowShr2, 0xF, 0xF));
+    v = min(v, LCPX_DPP(I, x, kDppRowShr3, 0xF, 0xF));
+    v = min(v, LCPX_DPP(I, v, kDppRowShr4, 0xF, 0xE));
+    v = min(v, LCPX_DPP(I, v, kDppRowShr8, 0xF, 0xC));
+    v = min(v, LCPX_DPP(I, v, kDppRowBcast15, 0xA, 0xF));
+    v = min(v, LCPX_DPP(I, v, kDppRowBcast31, 0xC, 0xF));
     return v;
 }
 
-// minimum over the wave's lanes (every lane gets it; call with all lanes
-// active).  Within each row of 16 lanes, DPP lane permutations (swap
-// neighbours, swap pairs, mirror each half, mirror the row) leave every lane
-// with its row's minimum; the four row minima are then read as scalars.
-__device__ __forceinline__ uint32_t dpp_min_step(uint32_t v, uint32_t o) { return o < v ? o : v; }
+// minimum over the wave's lanes, as a scalar (call with all lanes active).
+// Swapping neighbours, swapping pairs, mirroring each half row and mirroring
+// the row leave every lane with its row's minimum; lane 15 of each row then
+// goes into the next row and lane 31 into the upper half, so lane 63 holds
+// the minimum of all 64.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-    v = dpp_min_step(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
-    const uint32_t a = readlane(v, 0), b = readlane(v, 16), c = readlane(v, 32), d = readlane(v, 48);
-    const uint32_t ab = a < b ? a : b, cd = c < d ? c : d;
-    return ab < cd ? ab : cd;
+    constexpr int I = -1;  // 0xFFFFFFFF
+    v = min(v, (uint32_t)LCPX_DPP(I, (int)v, kDppQuadSwap1, 0xF, 0xF));
+    v = min(v, (uint32_t)LCPX_DPP(I, (int)v, kDppQuadSwap2, 0xF, 0xF));
+    v = min(v, (uint32_t)LCPX_DPP(I, (int)v, kDppRowHalfMirror, 0xF, 0xF));
+    v = min(v, (uint32_t)LCPX_DPP(I, (int)v, kDppRowMirror, 0xF, 0xF));
+    v = min(v, (uint32_t)LCPX_DPP(I, (int)v, kDppRowBcast15, 0xA, 0xF));
+    v = min(v, (uint32_t)LCPX_DPP(I, (int)v, kDppRowBcast31, 0xC, 0xF));
+    return readlane(v, kWave - 1);
 }
+#undef LCPX_DPP
 
 // ---------------------------------------------------------------- rows
 //

@@ -484,11 +484,16 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     const int64_t tn = tnl + (r - in_hi);
     const bool held = m > 0 && c > 0 && m <= kSelMax && tn <= kTieUnroll * kWave;
     uint32_t tid[kTieUnroll];
+    {
+        // positions fit in 32 bits (N < 2^31); t < tnl picks the left part
+        const int tnl32 = (int)tnl, tn32 = held ? (int)tn : 0;
+        const uint32_t lb = (uint32_t)l, rb = (uint32_t)in_hi - (uint32_t)tnl32;
 #pragma unroll
-    for (int u = 0; u < kTieUnroll; ++u) {
-        const int64_t t = u * kWave + lane;
-        const int64_t j = t < tnl ? l + t : in_hi + (t - tnl);
-        tid[u] = held && t < tn ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;  // above every id
+        for (int u = 0; u < kTieUnroll; ++u) {
+            const int t = u * kWave + lane;
+            const uint32_t j = (t < tnl32 ? lb : rb) + (uint32_t)t;
+            tid[u] = t < tn32 ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;  // above every id
+        }
     }
 
     // ---- 3. inner group G_{c+1}, ranked by (LCP desc, id asc)
@@ -576,7 +581,8 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             uint32_t mine = 0xFFFFFFFFu;  // lane e keeps the e-th smallest
             for (int e = 0; e < m; ++e) {
                 const uint32_t v = wave_min_u32(h0);
-                if (lane == e) mine = v;
+                // lane e takes v: one lane write instead of a compare and a select
+                asm("v_writelane_b32 %0, %1, m0" : "+v"(mine) : "s"(v), "{m0}"(e));
                 if (h0 == v) {  // one lane: the ids are distinct
                     h0 = h1;
                     h1 = h2;
