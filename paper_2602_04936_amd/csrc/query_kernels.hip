@@ -369,7 +369,9 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             const bool act = lane < n;
             int lc;
             bool less;
-            compare_row<VEC>(ix.sorted + (act ? lo + lane : 0) * g.W, q, g, act, lc, less);
+            // the wave's first row address is uniform; lanes add lane * W
+            const uint32_t* rows = ix.sorted + lo * g.W;
+            compare_row<VEC>(act ? rows + __umul24((unsigned)lane, (unsigned)g.W) : ix.sorted, q, g, act, lc, less);
             *reinterpret_cast<uint4*>(win + 16 * lane) = av;
             const int cnt = popc64(ballot(less));
             p = lo + cnt;
@@ -377,7 +379,10 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             lR = cnt < n ? readlane_i(lc, cnt) : lcp_hi;
             break;
         }
-        const int64_t pos = lo + ((int64_t)(lane + 1) * n) / (kWave + 1);
+        // lane i's pivot is row lo + (i + 1) * n / 65; only the rare paths
+        // that read pivot rows need it per lane, the chosen child's bounds
+        // below are computed from the (uniform) count
+        const uint64_t un = (uint64_t)n;
         int lc;
         bool less;
         if (depth < ix.stab_levels) {
@@ -394,6 +399,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             } else {  // tie on the first four words: compare the rest of the row
                 lc = g.L;
                 less = false;
+                const int64_t pos = lo + (int64_t)(((uint64_t)(lane + 1) * un) / (kWave + 1));
                 const uint32_t* row = ix.sorted + pos * g.W;
                 for (int w = 4; w < g.W; ++w) {
                     const uint32_t rw = row[w];
@@ -405,15 +411,17 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 }
             }
         } else {
+            const int64_t pos = lo + (int64_t)(((uint64_t)(lane + 1) * un) / (kWave + 1));
             compare_row<VEC>(ix.sorted + pos * g.W, q, g, true, lc, less);
         }
         const int cnt = popc64(ballot(less));  // pivots below q form a prefix of the lanes
-        if (cnt > 0) {
-            lo = readlane_i64(pos, cnt - 1) + 1;
+        const int64_t lo0 = lo;
+        if (cnt > 0) {  // just above pivot cnt - 1
+            lo = lo0 + (int64_t)(((uint64_t)cnt * un) / (kWave + 1)) + 1;
             lcp_lo = readlane_i(lc, cnt - 1);
         }
-        if (cnt < kWave) {
-            hi = readlane_i64(pos, cnt);
+        if (cnt < kWave) {  // up to pivot cnt
+            hi = lo0 + (int64_t)(((uint64_t)(cnt + 1) * un) / (kWave + 1));
             lcp_hi = readlane_i(lc, cnt);
         }
         if (depth < ix.stab_levels) {
