@@ -71,7 +71,8 @@ typedef enum {
  *
  *   tokens : device, [N][L] uint8 (V <= 256) or uint16 (V > 256).  The
  *            index copies them; the caller may free `tokens` after return.
- *   N      : 1 <= N < 2^31.      L : 1 <= L <= LCP_L_MAX.
+ *   N      : 1 <= N <= 2^31 - 2^16 (positions stay 32-bit).
+ *   L      : 1 <= L <= LCP_L_MAX.
  *   V      : 1 <= V <= 65536; every token must be < V.
  *   stream : stream the build runs on; the call synchronises it before it
  *            returns, so the index is ready on return.
@@ -139,7 +140,7 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
  * adjacent-LCP array and search tables are recomputed.
  *
  *   tokens : device, [n][L], same width as the index; every token < V.
- *   n      : 0 <= n, N + n < 2^31 (n = 0 is a no-op).
+ *   n      : 0 <= n, N + n <= 2^31 - 2^16 (n = 0 is a no-op).
  *   stream : the call first synchronises every stream the index has been used
  *            on, then runs on `stream` and synchronises it before returning.
  *            No query may run on the index during the call.

@@ -510,7 +510,7 @@ lcp_status lcp_index_build(const void* tokens, int64_t N, int32_t L, int32_t V, 
     if (!out) return fail(LCP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!tokens) return fail(LCP_EINVAL, "tokens is NULL");
-    if (N < 1 || N > INT32_MAX) return fail(LCP_EINVAL, "N = %lld is outside [1, 2^31)", (long long)N);
+    if (N < 1 || N > kMaxRows) return fail(LCP_EINVAL, "N = %lld is outside [1, 2^31 - 2^16]", (long long)N);
     if (L < 1 || L > LCP_L_MAX) return fail(LCP_EINVAL, "L = %d is outside [1, %d]", L, LCP_L_MAX);
     if (V < 1 || V > 65536) return fail(LCP_EINVAL, "V = %d is outside [1, 65536]", V);
     lcp_index* idx = new lcp_index();
@@ -595,8 +595,8 @@ lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, voi
     if (!index) return fail(LCP_EINVAL, "index is NULL");
     if (n == 0) return LCP_OK;
     if (!tokens) return fail(LCP_EINVAL, "tokens is NULL");
-    if (n < 0 || index->N + n > INT32_MAX)
-        return fail(LCP_EINVAL, "n = %lld would take N past 2^31 - 1", (long long)n);
+    if (n < 0 || index->N + n > kMaxRows)
+        return fail(LCP_EINVAL, "n = %lld would take N past 2^31 - 2^16", (long long)n);
     std::lock_guard<std::mutex> lk(index->mu);
     HIP_TRY(hipSetDevice(index->device));
     return append_into(index, tokens, n, static_cast<hipStream_t>(stream));

@@ -41,6 +41,9 @@ inline int64_t block_min_entries(int64_t N) { return (N + kWave - 1) / kWave; }
 hipError_t launch_block_min(const int32_t* perm, int64_t N, uint32_t* bmin, hipStream_t s);
 
 // ---- queries
+// Largest index: positions, and the A window reads up to kAdjPad past the
+// end, stay below 2^31, so the query kernels keep positions in 32 bits.
+constexpr int64_t kMaxRows = ((int64_t)1 << 31) - ((int64_t)1 << 16);
 constexpr int kAdjWindow = 1024;                  // bytes of A one query wave stages in LDS
 constexpr size_t kAdjPad = kAdjWindow + 64;       // zero bytes allocated past A[N-1]
 

@@ -43,12 +43,12 @@ constexpr int kSelMax = kAdjWindow / 4;  // 32-bit entries of the LDS window the
 // A[j] for the 64 positions j = j0 + dir * lane: from the wave's LDS window
 // when the whole chunk lies inside it, else from global memory.  Lanes whose
 // position is outside [lo_ok, hi_ok] get -1.
-__device__ __forceinline__ int a_lane(const uint8_t* __restrict__ A, const uint8_t* win, int64_t wbase, int64_t j0,
-                                      int dir, int64_t lo_ok, int64_t hi_ok) {
+__device__ __forceinline__ int a_lane(const uint8_t* __restrict__ A, const uint8_t* win, int wbase, int j0, int dir,
+                                      int lo_ok, int hi_ok) {
     const int lane = lane_id();
-    const int64_t j = j0 + dir * lane;
-    const int64_t jmin = dir > 0 ? j0 : j0 - (kWave - 1);
-    const int64_t jmax = dir > 0 ? j0 + (kWave - 1) : j0;
+    const int j = j0 + dir * lane;
+    const int jmin = dir > 0 ? j0 : j0 - (kWave - 1);
+    const int jmax = dir > 0 ? j0 + (kWave - 1) : j0;
     const bool in_win = jmin >= wbase && jmax < wbase + kAdjWindow;
     if (j < lo_ok || j > hi_ok) return -1;
     return in_win ? (int)win[j - wbase] : (int)A[j];
@@ -60,29 +60,29 @@ __device__ __forceinline__ int a_lane(const uint8_t* __restrict__ A, const uint8
 // are held in registers (two chunks of 64 per side) until the last A read,
 // then compacted into the wave's LDS window; each key's rank is the number of
 // keys below it.
-__device__ __forceinline__ void inner_by_rank(const IndexView& ix, uint8_t* win, int64_t wbase, int64_t p,
-                                              int64_t in_lo, int64_t in_hi, int lL, int lR, int n_gt,
-                                              int32_t* __restrict__ oid, int32_t* __restrict__ olc) {
+__device__ __forceinline__ void inner_by_rank(const IndexView& ix, uint8_t* win, int wbase, int p, int in_lo,
+                                              int in_hi, int lL, int lR, int n_gt, int32_t* __restrict__ oid,
+                                              int32_t* __restrict__ olc) {
     const int lane = lane_id();
-    const int64_t nr = in_hi - p;
-    const int64_t nl = p - in_lo;
+    const int nr = in_hi - p;
+    const int nl = p - in_lo;
     uint32_t id[2][2];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {  // all perm loads in flight first
-            const int64_t t = b * kWave + lane;
+            const int t = b * kWave + lane;
             const bool act = t < (sd == 0 ? nr : nl);
             id[sd][b] = act ? (uint32_t)ix.perm[sd == 0 ? p + t : p - 1 - t] : 0u;
         }
     uint64_t key[2][2];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd) {
-        const int64_t n = sd == 0 ? nr : nl;
+        const int n = sd == 0 ? nr : nl;
         int carry = 255;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const int64_t t = b * kWave + lane;
+            const int t = b * kWave + lane;
             key[sd][b] = kKeyMax;
             if (b * kWave < n) {
                 // right: row p+t needs A[p+t]; left: row p-1-t needs A[p-t]
@@ -104,7 +104,7 @@ __device__ __forceinline__ void inner_by_rank(const IndexView& ix, uint8_t* win,
     for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const int64_t t = b * kWave + lane;
+            const int t = b * kWave + lane;
             if (t < (sd == 0 ? nr : nl)) s64[sd == 0 ? t : nr + t] = key[sd][b];
         }
     const int n2 = (n_gt + 1) & ~1;
@@ -340,37 +340,37 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    const int64_t N = ix.N;
+    const int N = (int)ix.N;  // at most kMaxRows: positions and window offsets fit in 32 bits
     const int k = query_k(qb, qi);
     const int64_t out0 = query_off(qb, qi);
     int32_t* __restrict__ oid = qb.out_ids + out0;
     int32_t* __restrict__ olc = qb.out_lcp + out0;
-    const int kp = (int)((int64_t)k < N ? (int64_t)k : N);
+    const int kp = k < N ? k : N;
 
     // ---- 1. insertion point and the LCPs of its two neighbours
     // the query's first four key words as two 64-bit halves (zero past the row's end)
     const uint64_t qa = ((uint64_t)q[0] << 32) | (g.W > 1 ? q[1] : 0u);
     const uint64_t qb2 = ((uint64_t)(g.W > 2 ? q[2] : 0u) << 32) | (g.W > 3 ? q[3] : 0u);
-    int64_t lo = 0, hi = N;
+    int lo = 0, hi = N;
     int lcp_lo = -1, lcp_hi = -1;  // LCP(q, T[lo-1]), LCP(q, T[hi])
-    int64_t p;
+    int p;
     int lL, lR;
-    int64_t wbase;
+    int wbase;
     int depth = 0;
-    int64_t node = 0, level_start = 0;  // table node and the entry where its level starts
+    int node = 0, level_start = 0;  // table node and the entry where its level starts
     for (;;) {
-        const int64_t n = hi - lo;
+        const int n = hi - lo;
         if (n <= kWave) {
             // last step: the rows [lo, hi) are contiguous; the A window around
             // lo (p is within 64 of it) is fetched in the same round trip
             wbase = lo - kAdjWindow / 2;
-            wbase = wbase < 0 ? 0 : wbase & ~(int64_t)15;
+            wbase = wbase < 0 ? 0 : wbase & ~15;
             const uint4 av = *reinterpret_cast<const uint4*>(ix.A + wbase + 16 * lane);
             const bool act = lane < n;
             int lc;
             bool less;
             // the wave's first row address is uniform; lanes add lane * W
-            const uint32_t* rows = ix.sorted + lo * g.W;
+            const uint32_t* rows = ix.sorted + (int64_t)lo * g.W;
             compare_row<VEC>(act ? rows + __umul24((unsigned)lane, (unsigned)g.W) : ix.sorted, q, g, act, lc, less);
             *reinterpret_cast<uint4*>(win + 16 * lane) = av;
             const int cnt = popc64(ballot(less));
@@ -379,10 +379,12 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             lR = cnt < n ? readlane_i(lc, cnt) : lcp_hi;
             break;
         }
-        // lane i's pivot is row lo + (i + 1) * n / 65; only the rare paths
-        // that read pivot rows need it per lane, the chosen child's bounds
-        // below are computed from the (uniform) count
-        const uint64_t un = (uint64_t)n;
+        // lane i's pivot is row lo + (i + 1) * n / 65, computed in 32 bits as
+        // lo + (i + 1) * a + (i + 1) * b / 65 with n = 65 a + b; only the rare
+        // paths that read pivot rows need it per lane, the chosen child's
+        // bounds below come from the (uniform) count
+        const int a65 = (int)((uint32_t)n / (kWave + 1));
+        const int b65 = n - (kWave + 1) * a65;
         int lc;
         bool less;
         if (depth < ix.stab_levels) {
@@ -399,8 +401,8 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             } else {  // tie on the first four words: compare the rest of the row
                 lc = g.L;
                 less = false;
-                const int64_t pos = lo + (int64_t)(((uint64_t)(lane + 1) * un) / (kWave + 1));
-                const uint32_t* row = ix.sorted + pos * g.W;
+                const int pos = lo + (lane + 1) * a65 + (int)((uint32_t)((lane + 1) * b65) / (kWave + 1));
+                const uint32_t* row = ix.sorted + (int64_t)pos * g.W;
                 for (int w = 4; w < g.W; ++w) {
                     const uint32_t rw = row[w];
                     if (rw != q[w]) {
@@ -411,17 +413,17 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 }
             }
         } else {
-            const int64_t pos = lo + (int64_t)(((uint64_t)(lane + 1) * un) / (kWave + 1));
-            compare_row<VEC>(ix.sorted + pos * g.W, q, g, true, lc, less);
+            const int pos = lo + (lane + 1) * a65 + (int)((uint32_t)((lane + 1) * b65) / (kWave + 1));
+            compare_row<VEC>(ix.sorted + (int64_t)pos * g.W, q, g, true, lc, less);
         }
         const int cnt = popc64(ballot(less));  // pivots below q form a prefix of the lanes
-        const int64_t lo0 = lo;
+        const int lo0 = lo;
         if (cnt > 0) {  // just above pivot cnt - 1
-            lo = lo0 + (int64_t)(((uint64_t)cnt * un) / (kWave + 1)) + 1;
+            lo = lo0 + cnt * a65 + (int)((uint32_t)(cnt * b65) / (kWave + 1)) + 1;
             lcp_lo = readlane_i(lc, cnt - 1);
         }
         if (cnt < kWave) {  // up to pivot cnt
-            hi = lo0 + (int64_t)(((uint64_t)(cnt + 1) * un) / (kWave + 1));
+            hi = lo0 + (cnt + 1) * a65 + (int)((uint32_t)((cnt + 1) * b65) / (kWave + 1));
             lcp_hi = readlane_i(lc, cnt);
         }
         if (depth < ix.stab_levels) {
@@ -432,11 +434,11 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     }
 
     // ---- 2. walk outward level by level: group [l, r) = G_lev
-    int64_t l = p, r = p;
+    int l = p, r = p;
     int vr = p < N ? lR : -1;  // LCP(q, T[r]), -1 past the end
     int vl = p > 0 ? lL : -1;  // LCP(q, T[l-1]), -1 before the start
     int lev = vr > vl ? vr : vl;
-    int64_t in_lo = p, in_hi = p;  // G_{c+1}
+    int in_lo = p, in_hi = p;  // G_{c+1}
     int c;
     for (;;) {
         if (lev <= 0) {
@@ -446,7 +448,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             break;
         }
         if (vr >= lev) {  // T[r] is in: extend to the first j > r with A[j] < lev
-            for (int64_t j0 = r + 1;; j0 += kWave) {
+            for (int j0 = r + 1;; j0 += kWave) {
                 const int a = a_lane(ix.A, win, wbase, j0, +1, 1, N - 1);  // -1 past the end stops
                 const uint64_t stop = ballot(a < lev);
                 if (stop) {
@@ -458,12 +460,12 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             }
         }
         if (vl >= lev) {  // T[l-1] is in: extend down to the first i <= l-1 with A[i] < lev
-            for (int64_t i0 = l - 1;; i0 -= kWave) {
+            for (int i0 = l - 1;; i0 -= kWave) {
                 const int a = a_lane(ix.A, win, wbase, i0, -1, 1, N - 1);  // -1 at i < 1 stops
                 const uint64_t stop = ballot(a < lev);
                 if (stop) {
                     const int f = low_lane(stop);
-                    const int64_t ii = i0 - f;
+                    const int ii = i0 - f;
                     if (ii >= 1) {
                         l = ii;
                         vl = readlane_i(a, f);
@@ -488,13 +490,13 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
 
     // ids of a short tied range are requested now, so that their round trip
     // overlaps the inner group's
-    const int64_t tnl = in_lo - l;
-    const int64_t tn = tnl + (r - in_hi);
+    const int tnl = in_lo - l;
+    const int tn = tnl + (r - in_hi);
     const bool held = m > 0 && c > 0 && m <= kSelMax && tn <= kTieUnroll * kWave;
     uint32_t tid[kTieUnroll];
     {
         // positions fit in 32 bits (N < 2^31); t < tnl picks the left part
-        const int tnl32 = (int)tnl, tn32 = held ? (int)tn : 0;
+        const int tnl32 = tnl, tn32 = held ? tn : 0;
         const uint32_t lb = (uint32_t)l, rb = (uint32_t)in_hi - (uint32_t)tnl32;
 #pragma unroll
         for (int u = 0; u < kTieUnroll; ++u) {
@@ -558,9 +560,9 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             const uint32_t q0 = q[0];
             const int drop = 32 - 8 * g.tb;
             int got = 0;
-            for (int64_t b = 0; got < m && b < N; b += kWave) {
-                const int64_t id = b + lane;
-                const bool hit = id < N && ((ix.rows[id * g.W] ^ q0) >> drop) != 0u;
+            for (int b = 0; got < m && b < N; b += kWave) {
+                const int id = b + lane;
+                const bool hit = id < N && ((ix.rows[(int64_t)id * g.W] ^ q0) >> drop) != 0u;
                 const uint64_t bal = ballot(hit);
                 const int rank = got + count_below(bal);
                 if (hit && rank < m) {
@@ -608,7 +610,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             }
         } else if (held) {
             tied_select(ix, tid, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
-        } else if (m <= kSelMax && (in_lo - l) + (r - in_hi) >= (int64_t)kWave * 4 * (m > 8 ? m : 8)) {
+        } else if (m <= kSelMax && (in_lo - l) + (r - in_hi) >= kWave * 4 * (m > 8 ? m : 8)) {
             tied_pruned<NR>(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else {
             WaveList<NR> tied;

@@ -51,6 +51,9 @@ def test_error_paths_without_gpu():
     assert lib.lcp_index_build(dummy, 0, 4, 16, None, ctypes.byref(h)) == -1
     assert lib.lcp_index_build(dummy, 10, 256, 16, None, ctypes.byref(h)) == -1
     assert lib.lcp_index_build(dummy, 10, 4, 65537, None, ctypes.byref(h)) == -1
+    # the row limit keeps positions (and the A window past the end) below 2^31
+    assert lib.lcp_index_build(dummy, (1 << 31) - (1 << 16) + 1, 4, 16, None, ctypes.byref(h)) == -1
+    assert b"2^31 - 2^16" in lib.lcp_last_error()
     assert h.value is None
     lib.lcp_topk.restype = ctypes.c_int
     lib.lcp_topk.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] + [ctypes.c_void_p] * 4
