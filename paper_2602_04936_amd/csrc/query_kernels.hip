@@ -51,7 +51,10 @@ __device__ __forceinline__ int a_lane(const uint8_t* __restrict__ A, const uint8
     const int jmax = dir > 0 ? j0 + (kWave - 1) : j0;
     const bool in_win = jmin >= wbase && jmax < wbase + kAdjWindow;
     if (j < lo_ok || j > hi_ok) return -1;
-    return in_win ? (int)win[j - wbase] : (int)A[j];
+    // the window is read through an LDS pointer: a select between the two
+    // pointers would otherwise become one generic (flat) load on both paths
+    if (in_win) return (int)((const __attribute__((address_space(3))) uint8_t*)win)[j - wbase];
+    return (int)A[j];
 }
 
 // Inner group G_{c+1} = [in_lo, in_hi) around p, fewer than 128 rows, in rank
