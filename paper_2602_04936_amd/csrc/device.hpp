@@ -150,8 +150,11 @@ __device__ __forceinline__ int lcp_from_diff(int word, uint32_t x, const RowGeo&
 }
 
 // Per-lane LCP and order of a stored row against a query held in LDS.
-// Lanes with act == false return lcp = -1, less = false.  The loop leaves as
-// soon as every active lane has found its first differing word.
+// Lanes with act == false return lcp = -1, less = false; their `row` must
+// still point at a stored row (any), since every lane loads each word group.
+// Within a group the first differing word is picked with selects, not
+// per-lane branches; the loop leaves as soon as every active lane has found
+// its first differing word.  W is a multiple of VEC.
 template <int VEC>
 __device__ __forceinline__ void compare_row(const uint32_t* __restrict__ row, const uint32_t* q, const RowGeo& g,
                                             bool act, int& lcp, bool& less) {
@@ -160,28 +163,33 @@ __device__ __forceinline__ void compare_row(const uint32_t* __restrict__ row, co
     bool lt = false;
     bool open = act;
     for (int w = 0; w < g.W; w += VEC) {
-        if (open) {
-            uint32_t r[VEC];
-            if constexpr (VEC == 4) {
-                uint4 v = *reinterpret_cast<const uint4*>(row + w);
-                r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
-            } else if constexpr (VEC == 2) {
-                uint2 v = *reinterpret_cast<const uint2*>(row + w);
-                r[0] = v.x; r[1] = v.y;
-            } else {
-                r[0] = row[w];
-            }
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                uint32_t qq = q[w + j];
-                if (open && r[j] != qq) {
-                    fw = w + j;
-                    fx = r[j] ^ qq;
-                    lt = r[j] < qq;
-                    open = false;
-                }
-            }
+        uint32_t r[VEC];
+        if constexpr (VEC == 4) {
+            const uint4 v = *reinterpret_cast<const uint4*>(row + w);
+            r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+        } else if constexpr (VEC == 2) {
+            const uint2 v = *reinterpret_cast<const uint2*>(row + w);
+            r[0] = v.x; r[1] = v.y;
+        } else {
+            r[0] = row[w];
         }
+        int gw = -1;  // first differing word of this group (scanned from the last)
+        uint32_t gx = 0;
+        bool glt = false;
+#pragma unroll
+        for (int j = VEC - 1; j >= 0; --j) {
+            const uint32_t qq = q[w + j];
+            const uint32_t x = r[j] ^ qq;
+            const bool d = x != 0u;
+            gw = d ? w + j : gw;
+            gx = d ? x : gx;
+            glt = d ? r[j] < qq : glt;
+        }
+        const bool take = open && gw >= 0;
+        fw = take ? gw : fw;
+        fx = take ? gx : fx;
+        lt = take ? glt : lt;
+        open = open && gw < 0;
         if (ballot(open) == 0) break;
     }
     lcp = act ? (fw < 0 ? g.L : lcp_from_diff(fw, fx, g)) : -1;

@@ -395,23 +395,25 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             const uint4 e = depth == 0 ? root : ix.stab[level_start + node * kWave + lane];
             const uint64_t ka = ((uint64_t)e.x << 32) | e.y;
             const uint64_t kb = ((uint64_t)e.z << 32) | e.w;
-            if (ka != qa) {
-                lc = (int)(__clzll((long long)(ka ^ qa)) >> g.bits_log2);
-                less = ka < qa;
-            } else if (kb != qb2) {
-                lc = (int)((64 + __clzll((long long)(kb ^ qb2))) >> g.bits_log2);
-                less = kb < qb2;
-            } else {  // tie on the first four words: compare the rest of the row
-                lc = g.L;
-                less = false;
-                const int pos = lo + (lane + 1) * a65 + (int)((uint32_t)((lane + 1) * b65) / (kWave + 1));
-                const uint32_t* row = ix.sorted + (int64_t)pos * g.W;
-                for (int w = 4; w < g.W; ++w) {
-                    const uint32_t rw = row[w];
-                    if (rw != q[w]) {
-                        lc = lcp_from_diff(w, rw ^ q[w], g);
-                        less = rw < q[w];
-                        break;
+            // first differing 64-bit half by selects (no per-lane branches)
+            const uint64_t xa = ka ^ qa, xb = kb ^ qb2;
+            const bool da = xa != 0;
+            lc = (int)(((da ? 0 : 64) + __clzll((long long)(da ? xa : xb))) >> g.bits_log2);
+            less = da ? ka < qa : kb < qb2;
+            const bool tie = !da && xb == 0;
+            if (ballot(tie)) {  // a pivot ties on the first four words: compare the rest of its row
+                if (tie) {
+                    lc = g.L;
+                    less = false;
+                    const int pos = lo + (lane + 1) * a65 + (int)((uint32_t)((lane + 1) * b65) / (kWave + 1));
+                    const uint32_t* row = ix.sorted + (int64_t)pos * g.W;
+                    for (int w = 4; w < g.W; ++w) {
+                        const uint32_t rw = row[w];
+                        if (rw != q[w]) {
+                            lc = lcp_from_diff(w, rw ^ q[w], g);
+                            less = rw < q[w];
+                            break;
+                        }
                     }
                 }
             }
