@@ -84,6 +84,21 @@ __device__ __forceinline__ int wave_prefix_min(int v) {
     return v;
 }
 
+// inclusive prefix sum over the wave's lanes (call with all lanes active):
+// the same shift pattern as the prefix minimum, with 0 for lanes left out
+__device__ __forceinline__ uint32_t wave_prefix_sum(uint32_t v) {
+    const int x = (int)v;
+    int s = x;
+    s += LCPX_DPP(0, x, kDppRowShr1, 0xF, 0xF);
+    s += LCPX_DPP(0, x, kDppRowShr2, 0xF, 0xF);
+    s += LCPX_DPP(0, x, kDppRowShr3, 0xF, 0xF);
+    s += LCPX_DPP(0, s, kDppRowShr4, 0xF, 0xE);
+    s += LCPX_DPP(0, s, kDppRowShr8, 0xF, 0xC);
+    s += LCPX_DPP(0, s, kDppRowBcast15, 0xA, 0xF);
+    s += LCPX_DPP(0, s, kDppRowBcast31, 0xC, 0xF);
+    return (uint32_t)s;
+}
+
 // minimum over the wave's lanes, as a scalar (call with all lanes active).
 // Swapping neighbours, swapping pairs, mirroring each half row and mirroring
 // the row leave every lane with its row's minimum; lane 15 of each row then

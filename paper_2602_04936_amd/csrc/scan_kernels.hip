@@ -50,10 +50,6 @@ __device__ __forceinline__ void limit_filter(uint64_t lim, int64_t next_id, uint
     }
 }
 
-__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
 
 // Starting limits from the first S rows (ids 0..S-1).  hist[q][d] counts the
 // sample rows with LCP exactly d.  With t the largest d such that at least k'
@@ -113,22 +109,33 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const 
         if (h[i]) atomicAdd(hist + qi * (g.L + 1) + i, h[i]);
 }
 
-__global__ void k_seed_limit(QueryBatch qb, int64_t N, int L, int64_t S, const uint32_t* __restrict__ hist,
-                             uint64_t* __restrict__ gthr) {
-    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per query.  Lane i takes d = top - i, so the wave's inclusive
+// prefix sum at lane i counts the sample rows with LCP in [d, top] (plus the
+// rows above top from earlier passes); the first lane where it reaches k'
+// gives the largest d with at least k' sample rows of LCP >= d.  All of a
+// pass's histogram loads are in flight at once.
+__global__ __launch_bounds__(kScanWaves * kWave) void k_seed_limit(QueryBatch qb, int64_t N, int L, int64_t S,
+                                                                   const uint32_t* __restrict__ hist,
+                                                                   uint64_t* __restrict__ gthr) {
+    const int lane = lane_id();
+    const int64_t qi = (int64_t)blockIdx.x * kScanWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (qi >= qb.Q) return;
     const int k = query_k(qb, qi);
-    const int64_t kk = (int64_t)k < N ? (int64_t)k : N;
-    int64_t acc = 0;
+    const uint32_t kk = (uint32_t)((int64_t)k < N ? (int64_t)k : N);
+    const uint32_t* h = hist + qi * (L + 1);
     uint64_t lim = kKeyMax;
-    for (int d = L; d >= 0; --d) {
-        acc += hist[qi * (L + 1) + d];
-        if (acc >= kk) {
-            lim = rank_key(d, (uint32_t)S);
+    uint32_t above = 0;  // sample rows with LCP above this pass's top
+    for (int top = L; top >= 0; top -= kWave) {
+        const int d = top - lane;
+        const uint32_t acc = wave_prefix_sum(d >= 0 ? h[d] : 0u) + above;
+        const uint64_t ok = ballot(d >= 0 && acc >= kk);
+        if (ok) {
+            lim = rank_key(top - low_lane(ok), (uint32_t)S);
             break;
         }
+        above = readlane(acc, kWave - 1);
     }
-    gthr[qi] = lim;
+    if (lane == 0) gthr[qi] = lim;
 }
 
 // gthr[q] holds the smallest k-th key any chunk has reached for query q: a row
@@ -149,12 +156,17 @@ struct ScanQueryState {  // per (wave, query), in LDS
     int32_t pad_;
 };
 
-// Query key words, computed once per launch for every block to copy.
-__global__ void k_query_keys(QueryBatch qb, RowGeo g, uint32_t* __restrict__ qkeys) {
+// One launch before the scan: zero the fill counts and histograms (a kernel,
+// not a memset, so the sequence can be captured in a graph) and compute the
+// query key words once for every block to copy.
+__global__ void k_scan_prep(QueryBatch qb, RowGeo g, uint32_t* __restrict__ zero, int64_t nz,
+                            uint32_t* __restrict__ qkeys) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= qb.Q * g.W) return;
-    const int64_t qi = t / g.W;
-    qkeys[t] = key_word(qb.raw, qi * g.L, g, (int)(t - qi * g.W));
+    if (t < nz) zero[t] = 0u;
+    if (t < qb.Q * g.W) {
+        const int64_t qi = t / g.W;
+        qkeys[t] = key_word(qb.raw, qi * g.L, g, (int)(t - qi * g.W));
+    }
 }
 
 // Blocks x < seed_chunks scan the sampled rows [0, seed_rows) in chunks of
@@ -352,6 +364,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
 }
 
 // Merge each query's partial list (cnt[q] entries) into its answer.
+constexpr int kMergeFew = 16;  // answers at most this many: repeated wave minima instead of the list
 template <int NR>
 __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb, int64_t N, int64_t cap,
                                                                    const uint64_t* __restrict__ part,
@@ -364,9 +377,67 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
     const int m = (int)((int64_t)k < N ? (int64_t)k : N);
     const int64_t total = (int64_t)cnt[qi];
     const uint64_t* src = part + qi * cap;
+    int32_t* oid = qb.out_ids + query_off(qb, qi);
+    int32_t* olc = qb.out_lcp + query_off(qb, qi);
+    constexpr int kMergeUnroll = 8;
+    if (m <= kMergeFew && total <= kMergeUnroll * kWave) {
+        // few answers from at most 512 entries: each lane sorts its (at most
+        // 8) keys, then m rounds take the smallest of the lanes' heads (the
+        // 64-bit minimum as two 32-bit wave minima: high words, then the low
+        // words of the heads with that high word; keys are distinct) and the
+        // lane holding it drops it
+        uint64_t h0, h1, h2, h3, h4, h5, h6, h7;
+        {
+            uint64_t key[kMergeUnroll];
+#pragma unroll
+            for (int u = 0; u < kMergeUnroll; ++u) {
+                const int64_t t = u * kWave + lane;
+                key[u] = t < total ? src[t] : kKeyMax;
+            }
+            h0 = key[0]; h1 = key[1]; h2 = key[2]; h3 = key[3];
+            h4 = key[4]; h5 = key[5]; h6 = key[6]; h7 = key[7];
+        }
+#define LCPX_CE64(x, y)                            \
+    {                                              \
+        const uint64_t lo_ = x < y ? x : y;        \
+        y = x < y ? y : x;                         \
+        x = lo_;                                   \
+    }
+        LCPX_CE64(h0, h1) LCPX_CE64(h2, h3) LCPX_CE64(h4, h5) LCPX_CE64(h6, h7) LCPX_CE64(h0, h2) LCPX_CE64(h1, h3)
+        LCPX_CE64(h4, h6) LCPX_CE64(h5, h7) LCPX_CE64(h1, h2) LCPX_CE64(h5, h6) LCPX_CE64(h0, h4) LCPX_CE64(h1, h5)
+        LCPX_CE64(h2, h6) LCPX_CE64(h3, h7) LCPX_CE64(h2, h4) LCPX_CE64(h3, h5) LCPX_CE64(h1, h2) LCPX_CE64(h3, h4)
+        LCPX_CE64(h5, h6)
+#undef LCPX_CE64
+        uint64_t mine = kKeyMax;  // lane e keeps the e-th smallest
+        for (int e = 0; e < m; ++e) {
+            const uint32_t hh = (uint32_t)(h0 >> 32);
+            const uint32_t mh = wave_min_u32(hh);
+            const uint32_t ml = wave_min_u32(hh == mh ? (uint32_t)h0 : 0xFFFFFFFFu);
+            const uint64_t v = ((uint64_t)mh << 32) | ml;
+            if (lane == e) mine = v;
+            if (h0 == v) {  // one lane
+                h0 = h1;
+                h1 = h2;
+                h2 = h3;
+                h3 = h4;
+                h4 = h5;
+                h5 = h6;
+                h6 = h7;
+                h7 = kKeyMax;
+            }
+        }
+        if (lane < m) {
+            oid[lane] = key_id(mine);
+            olc[lane] = key_lcp(mine);
+        }
+        for (int e = m + lane; e < k; e += kWave) {
+            oid[e] = -1;
+            olc[e] = -1;
+        }
+        return;
+    }
     WaveList<NR> lst;
     lst.init();
-    constexpr int kMergeUnroll = 8;
     for (int64_t b = 0; b < total; b += kMergeUnroll * kWave) {
         uint64_t key[kMergeUnroll];
 #pragma unroll
@@ -382,8 +453,6 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
             lst.offer(x, x != kKeyMax, m);
         }
     }
-    int32_t* oid = qb.out_ids + query_off(qb, qi);
-    int32_t* olc = qb.out_lcp + query_off(qb, qi);
 #pragma unroll
     for (int rr = 0; rr < NR; ++rr) {
         const int e = rr * kWave + lane;
@@ -496,13 +565,13 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
     if (qb.Q <= 0) return hipSuccess;
     const ScanScratch sc = scan_scratch(p, qb.Q, qb.k_max, ix.g, scratch);
     const int64_t nz = qb.Q * (int64_t)(1 + ix.g.L + 1);  // cnt and hist
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, sc.cnt, nz, 0u);
-    hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((qb.Q * ix.g.W + 255) / 256)), dim3(256), 0, s, qb, ix.g,
+    const int64_t nprep = nz > qb.Q * ix.g.W ? nz : qb.Q * ix.g.W;
+    hipLaunchKernelGGL(k_scan_prep, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, s, qb, ix.g, sc.cnt, nz,
                        sc.qkeys);
     hipLaunchKernelGGL(k_seed_hist, dim3((unsigned)(qb.Q * p.seed_parts)), dim3(kSeedThreads), 0, s, ix, sc.qkeys,
                        p.seed_rows, p.seed_parts, sc.hist);
-    hipLaunchKernelGGL(k_seed_limit, dim3((unsigned)((qb.Q + 255) / 256)), dim3(256), 0, s, qb, ix.N, ix.g.L,
-                       p.seed_rows, sc.hist, sc.gthr);
+    hipLaunchKernelGGL(k_seed_limit, dim3((unsigned)((qb.Q + kScanWaves - 1) / kScanWaves)), dim3(kScanWaves * kWave),
+                       0, s, qb, ix.N, ix.g.L, p.seed_rows, sc.hist, sc.gthr);
     if (ev0) hipEventRecord(ev0, s);
     switch (p.nr * 100 + p.tq) {
         case 108: launch_scan_t<1, 8>(ix, qb, p, sc, s); break;
