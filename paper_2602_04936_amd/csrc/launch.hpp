@@ -116,7 +116,7 @@ struct ScanScratch {
     int64_t cap;       // partial-list entries per query (nparts * k_max)
     uint64_t* part;    // [Q][cap]
     uint64_t* gthr;    // [Q] shared limits
-    uint32_t* cnt;     // [Q] partial entries appended
+    uint32_t* cnt;     // [Q] partial entries appended, one per 128-byte line
     uint32_t* hist;    // [Q][L+1] seed LCP histogram
     uint32_t* qkeys;   // [Q][W] query key words
     size_t words;      // total size in 32-bit words

@@ -23,6 +23,10 @@ namespace lcpx {
 constexpr int kScanWaves = 4;
 constexpr int kScanUnroll = 4;
 constexpr int64_t kSeedChunkRows = kScanUnroll * kWave;  // one step of a block
+// Each query's fill count sits on its own 128-byte line: every wave of every
+// chunk adds to the counts of its queries, and counts sharing a line would
+// serialise those atomics in one L2 channel.
+constexpr int kCntStride = 32;
 
 // Mask and masked query bits that a row's first two key words (as one 64-bit
 // value, word 0 high) must match for the row's rank key to beat `lim`
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         mine = lane == i ? n : mine;
     }
     uint32_t at = 0;
-    if (lane < ntq && mine > 0) at = atomicAdd(cnt + q0i + lane, (uint32_t)mine);
+    if (lane < ntq && mine > 0) at = atomicAdd(cnt + (q0i + lane) * kCntStride, (uint32_t)mine);
 #pragma unroll 1
     for (int i = 0; i < ntq; ++i) {
         const int n = readlane_i(mine, i);
@@ -375,7 +379,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
     if (qi >= qb.Q) return;
     const int k = query_k(qb, qi);
     const int m = (int)((int64_t)k < N ? (int64_t)k : N);
-    const int64_t total = (int64_t)cnt[qi];
+    const int64_t total = (int64_t)cnt[qi * kCntStride];
     const uint64_t* src = part + qi * cap;
     int32_t* oid = qb.out_ids + query_off(qb, qi);
     int32_t* olc = qb.out_lcp + query_off(qb, qi);
@@ -539,10 +543,10 @@ ScanScratch scan_scratch(const ScanPlan& p, int64_t Q, int32_t k_max, const RowG
     sc.part = base;
     sc.gthr = base + (size_t)Q * (size_t)sc.cap;
     uint32_t* u = reinterpret_cast<uint32_t*>(sc.gthr + Q);
-    sc.cnt = u;                                // [Q]      zeroed per call
-    sc.hist = u + Q;                           // [Q][L+1] zeroed per call
+    sc.cnt = u;                                // [Q][kCntStride], entry 0 used; zeroed per call
+    sc.hist = u + (size_t)Q * kCntStride;      // [Q][L+1] zeroed per call
     sc.qkeys = sc.hist + (size_t)Q * (g.L + 1);  // [Q][W]
-    sc.words = ((size_t)Q * (size_t)sc.cap + (size_t)Q) * 2 + (size_t)Q * (1 + (g.L + 1) + g.W);
+    sc.words = ((size_t)Q * (size_t)sc.cap + (size_t)Q) * 2 + (size_t)Q * (kCntStride + (g.L + 1) + g.W);
     return sc;
 }
 
@@ -564,7 +568,7 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
                        hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
     if (qb.Q <= 0) return hipSuccess;
     const ScanScratch sc = scan_scratch(p, qb.Q, qb.k_max, ix.g, scratch);
-    const int64_t nz = qb.Q * (int64_t)(1 + ix.g.L + 1);  // cnt and hist
+    const int64_t nz = qb.Q * (int64_t)(kCntStride + ix.g.L + 1);  // cnt and hist
     const int64_t nprep = nz > qb.Q * ix.g.W ? nz : qb.Q * ix.g.W;
     hipLaunchKernelGGL(k_scan_prep, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, s, qb, ix.g, sc.cnt, nz,
                        sc.qkeys);
