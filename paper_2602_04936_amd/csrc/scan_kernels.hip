@@ -497,9 +497,12 @@ ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     const int64_t per_group = (int64_t)kScanWaves * p.tq;
     p.qgroups = (int)((Q + per_group - 1) / per_group);
     p.seed_rows = N < kSeedRows ? N : kSeedRows;
-    // seed blocks per query: enough blocks in all to fill the device
+    // seed blocks per query: enough blocks in all to fill the device, but at
+    // most 32, since every block adds its counts to the query's histogram
+    // with global atomics on the same few addresses
     const int64_t seed_tiles = (p.seed_rows + 255) / 256;
     int64_t parts = Q > 0 ? 4096 / Q : 1;
+    if (parts > 32) parts = 32;
     if (parts > seed_tiles) parts = seed_tiles;
     p.seed_parts = (int)(parts < 1 ? 1 : parts);
     const int64_t bytes_per_chunk = Q * (int64_t)k_max * 8;
