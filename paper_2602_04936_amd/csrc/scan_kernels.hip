@@ -338,15 +338,15 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     }
 
     // entries above a valid limit cannot be in the answer; each list is
-    // ascending, so the kept ones are a prefix.  Lane i counts query i's and
+    // ascending, so the kept ones are a prefix.  The wave's own limit is used
+    // (the shared one may be tighter, but reading it would cost another round
+    // trip; the merge ranks whatever is kept).  Lane i counts query i's and
     // reserves room for them with one atomic for all the wave's queries.
-    const uint64_t gl = lane < ntq ? gthr[q0i + lane] : 0ull;
     int mine = 0;
 #pragma unroll 1
     for (int i = 0; i < ntq; ++i) {
         const int kk = st[i].kk;
-        const uint64_t g_i = readlane64(gl, i);
-        const uint64_t keep = g_i < st[i].lim ? g_i : st[i].lim;
+        const uint64_t keep = st[i].lim;
         int n = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -368,7 +368,8 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
 }
 
 // Merge each query's partial list (cnt[q] entries) into its answer.
-constexpr int kMergeFew = 16;  // answers at most this many: repeated wave minima instead of the list
+constexpr int kMergeFew = 16;        // answers at most this many, from at most
+constexpr int64_t kMergeFewMax = 4096;  // this many entries: repeated wave minima instead of the list
 template <int NR>
 __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb, int64_t N, int64_t cap,
                                                                    const uint64_t* __restrict__ part,
@@ -384,50 +385,54 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
     int32_t* oid = qb.out_ids + query_off(qb, qi);
     int32_t* olc = qb.out_lcp + query_off(qb, qi);
     constexpr int kMergeUnroll = 8;
-    if (m <= kMergeFew && total <= kMergeUnroll * kWave) {
-        // few answers from at most 512 entries: each lane sorts its (at most
-        // 8) keys, then m rounds take the smallest of the lanes' heads (the
+    if (m <= kMergeFew && total <= kMergeFewMax) {
+        // few answers: passes over the entries, each lane sorting at most 8
+        // keys, then m rounds take the smallest of the lanes' heads (the
         // 64-bit minimum as two 32-bit wave minima: high words, then the low
         // words of the heads with that high word; keys are distinct) and the
-        // lane holding it drops it
-        uint64_t h0, h1, h2, h3, h4, h5, h6, h7;
-        {
+        // lane holding it drops it.  The first pass reads 512 entries; each
+        // later pass reads 448 and carries the winners so far in the last
+        // register of lanes 0..m-1.
+        uint64_t mine = kKeyMax;  // lane e keeps the e-th smallest so far
+        for (int64_t b = 0; b < total;) {
+            const int fresh = b == 0 ? kMergeUnroll : kMergeUnroll - 1;
             uint64_t key[kMergeUnroll];
 #pragma unroll
             for (int u = 0; u < kMergeUnroll; ++u) {
-                const int64_t t = u * kWave + lane;
-                key[u] = t < total ? src[t] : kKeyMax;
+                const int64_t t = b + u * kWave + lane;
+                key[u] = u < fresh && t < total ? src[t] : kKeyMax;
             }
-            h0 = key[0]; h1 = key[1]; h2 = key[2]; h3 = key[3];
-            h4 = key[4]; h5 = key[5]; h6 = key[6]; h7 = key[7];
-        }
+            if (fresh < kMergeUnroll) key[kMergeUnroll - 1] = mine;
+            b += (int64_t)fresh * kWave;
+            uint64_t h0 = key[0], h1 = key[1], h2 = key[2], h3 = key[3];
+            uint64_t h4 = key[4], h5 = key[5], h6 = key[6], h7 = key[7];
 #define LCPX_CE64(x, y)                            \
     {                                              \
         const uint64_t lo_ = x < y ? x : y;        \
         y = x < y ? y : x;                         \
         x = lo_;                                   \
     }
-        LCPX_CE64(h0, h1) LCPX_CE64(h2, h3) LCPX_CE64(h4, h5) LCPX_CE64(h6, h7) LCPX_CE64(h0, h2) LCPX_CE64(h1, h3)
-        LCPX_CE64(h4, h6) LCPX_CE64(h5, h7) LCPX_CE64(h1, h2) LCPX_CE64(h5, h6) LCPX_CE64(h0, h4) LCPX_CE64(h1, h5)
-        LCPX_CE64(h2, h6) LCPX_CE64(h3, h7) LCPX_CE64(h2, h4) LCPX_CE64(h3, h5) LCPX_CE64(h1, h2) LCPX_CE64(h3, h4)
-        LCPX_CE64(h5, h6)
+            LCPX_CE64(h0, h1) LCPX_CE64(h2, h3) LCPX_CE64(h4, h5) LCPX_CE64(h6, h7) LCPX_CE64(h0, h2)
+            LCPX_CE64(h1, h3) LCPX_CE64(h4, h6) LCPX_CE64(h5, h7) LCPX_CE64(h1, h2) LCPX_CE64(h5, h6)
+            LCPX_CE64(h0, h4) LCPX_CE64(h1, h5) LCPX_CE64(h2, h6) LCPX_CE64(h3, h7) LCPX_CE64(h2, h4)
+            LCPX_CE64(h3, h5) LCPX_CE64(h1, h2) LCPX_CE64(h3, h4) LCPX_CE64(h5, h6)
 #undef LCPX_CE64
-        uint64_t mine = kKeyMax;  // lane e keeps the e-th smallest
-        for (int e = 0; e < m; ++e) {
-            const uint32_t hh = (uint32_t)(h0 >> 32);
-            const uint32_t mh = wave_min_u32(hh);
-            const uint32_t ml = wave_min_u32(hh == mh ? (uint32_t)h0 : 0xFFFFFFFFu);
-            const uint64_t v = ((uint64_t)mh << 32) | ml;
-            if (lane == e) mine = v;
-            if (h0 == v) {  // one lane
-                h0 = h1;
-                h1 = h2;
-                h2 = h3;
-                h3 = h4;
-                h4 = h5;
-                h5 = h6;
-                h6 = h7;
-                h7 = kKeyMax;
+            for (int e = 0; e < m; ++e) {
+                const uint32_t hh = (uint32_t)(h0 >> 32);
+                const uint32_t mh = wave_min_u32(hh);
+                const uint32_t ml = wave_min_u32(hh == mh ? (uint32_t)h0 : 0xFFFFFFFFu);
+                const uint64_t v = ((uint64_t)mh << 32) | ml;
+                if (lane == e) mine = v;
+                if (h0 == v && v != kKeyMax) {  // one lane (fewer than m entries leave only kKeyMax)
+                    h0 = h1;
+                    h1 = h2;
+                    h2 = h3;
+                    h3 = h4;
+                    h4 = h5;
+                    h5 = h6;
+                    h6 = h7;
+                    h7 = kKeyMax;
+                }
             }
         }
         if (lane < m) {
