@@ -493,7 +493,7 @@ static int tq_for(int nr, int64_t Q) {
 
 // Rows sampled for the starting limits, and the main pass's chunking.
 constexpr int64_t kChunkMinRows = 2048;
-constexpr int64_t kSeedRows = 32768;
+constexpr int64_t kSeedRows = 65536;
 
 ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     ScanPlan p;
