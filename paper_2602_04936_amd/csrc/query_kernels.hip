@@ -10,9 +10,10 @@
 //     (one per lane) and keeps the gap that contains q, so the insertion point
 //     is found in ceil(log_65(N)) dependent steps instead of log_2(N).  The
 //     top levels read the pivots' first four key words from the search tables
-//     (one coalesced 1 KB load per step, resident in L2) and touch a
-//     pivot row only on a tie; the last step reads its at most 64 contiguous
-//     rows.  The steps also yield lL = LCP(q, T[p-1]) and lR = LCP(q, T[p]).
+//     (one coalesced 1 KB load per step; the first two levels stay in L2) and
+//     touch a pivot row only on a tie; the last step reads its at most 64
+//     contiguous rows.  The steps also yield lL = LCP(q, T[p-1]) and
+//     lR = LCP(q, T[p]).
 //  2. Outward walk.  By the strong triangle inequality (section 2.1, Theorem
 //     "Ultrametric Property") and sorted order, LCP(q, T[j]) = min(lR,
 //     A[p+1..j]) for j >= p and min(lL, A[j+1..p-1]) for j < p: the LCP only

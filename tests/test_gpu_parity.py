@@ -317,6 +317,27 @@ def test_tie_selection_boundaries(P, T, n_gt, k):
     check_against_oracle(P, db, qs, [k, 1, k, max(1, k - 1)], 8, f"ties T={T} n_gt={n_gt} k={k}")
 
 
+@pytest.mark.parametrize("N,k", [(20000, 10), (300000, 1), (300000, 10), (300000, 16), (300000, 17)])
+def test_scan_merge_paths(P, N, k):
+    """Nearly every row ties with the query on its first L-1 tokens and a
+    quarter match it exactly, so every scan chunk keeps k entries: partial
+    lists of a few hundred to several thousand entries per query.  That covers
+    each merge path: the few-answer passes (k <= 16, one pass up to 512
+    entries, several passes up to 4,096) and the sorted list (k > 16, or more
+    than 4,096 entries)."""
+    rng = np.random.default_rng(N * 31 + k)
+    L = 8
+    q = rng.integers(0, 4, L).astype(np.uint8)
+    db = np.tile(q, (N, 1))
+    db[:, L - 1] = rng.integers(0, 4, N)
+    early = rng.choice(N, N // 10, replace=False)  # some rows leave the query's prefix earlier
+    db[early, 3] = (q[3] + 1 + rng.integers(0, 3, early.size)) % 4
+    other = q.copy()
+    other[0] = (q[0] + 1) % 4
+    qs = np.stack([q, q, q, other])
+    check_against_oracle(P, db, qs, [k, k, 1, k], 4, f"merge paths N={N} k={k}")
+
+
 def test_served_results_equal_alone(P):
     """Continuous batching on the GPU: every request's answer equals the
     oracle's answer for that request alone."""
