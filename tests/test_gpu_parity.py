@@ -303,10 +303,11 @@ def _tie_case(rng, T, n_gt, n_other=300, L=6):
 @pytest.mark.parametrize("T,n_gt,k", [
     (512, 0, 16), (512, 0, 17), (512, 3, 259), (513, 0, 17), (512, 0, 257), (64, 0, 64),
     (3000, 2, 12), (20000, 5, 200), (60000, 5, 200), (200, 127, 128), (200, 63, 64), (200, 64, 66),
-    (511, 120, 128)])
+    (511, 120, 128), (64, 0, 16), (65, 2, 16), (128, 0, 10), (129, 3, 12)])
 def test_tie_selection_boundaries(P, T, n_gt, k):
     """Each tie-selection path at its limits: wave minima (m <= 16, <= 512
-    tied rows), bisection select (m <= 256, <= 512 rows), pruned by block
+    tied rows, also at 64 and 128 rows), bisection select (m <= 256, <= 512
+    rows), pruned by block
     minima (long ranges), the sorted list otherwise; inner groups of up to
     127 rows ranked by counting."""
     rng = np.random.default_rng(T * 1000 + n_gt * 7 + k)
