@@ -64,7 +64,7 @@ constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
 
 // v combined with the value of another lane chosen by a DPP control; lanes
 // the control or the row/bank masks leave out take `ident`, the operation's
-// identity, so the combining min folds into one DPP instruction
+// identity, so the combining min or add folds into one DPP instruction
 #define LCPX_DPP(ident, v, ctrl, rmask, bmask) __builtin_amdgcn_update_dpp((ident), (v), (ctrl), (rmask), (bmask), false)
 
 // inclusive prefix minimum over the wave's lanes (call with all lanes
