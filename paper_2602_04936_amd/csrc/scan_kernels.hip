@@ -189,6 +189,12 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                                                              uint32_t* __restrict__ cnt,
                                                              uint64_t* __restrict__ gthr) {
     static_assert(kScanUnroll * TQ <= 64, "one flag bit per (tile, query)");
+    // bit u * TQ of each tile u: shifted by i, the bits of query i's tiles
+    constexpr uint64_t kTileBits = [] {
+        uint64_t b = 0;
+        for (int u = 0; u < kScanUnroll; ++u) b |= 1ull << (u * TQ);
+        return b;
+    }();
     extern __shared__ uint64_t s_dyn64[];
     ScanQueryState<NR>* st_all = reinterpret_cast<ScanQueryState<NR>*>(s_dyn64);  // [kScanWaves*TQ]
     uint32_t* s_q = reinterpret_cast<uint32_t*>(st_all + kScanWaves * TQ);       // [kScanWaves*TQ][W]
@@ -269,9 +275,6 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                 nx[u] = ix.plane[id < r_hi ? id : r_hi - 1];
             }
         }
-        uint64_t live[kScanUnroll];  // lanes holding a row of this chunk
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) live[u] = ballot(base + u * kWave + lane < r_hi);
         // filters stay in VGPRs (wave-uniform values): one AND pair and one
         // 64-bit compare per (tile, query)
         uint64_t msk[TQ], qm[TQ];
@@ -280,13 +283,18 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
             msk[i] = st[i].msk;
             qm[i] = st[i].qm;
         }
-        // hot loop: which (tile, query) pairs have a candidate lane
+        // hot loop: which queries have a candidate lane in any of the step's
+        // tiles (the tiles' ballots are OR-ed, one scalar op per pair); a
+        // flagged query gets a bit for each of its tiles, and the slow path
+        // skips tiles without a candidate.  Lanes past the chunk re-read its
+        // last row, so they may flag a query; the slow path drops them.
         uint64_t flagged = 0;
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
+        for (int i = 0; i < TQ; ++i) {
+            uint64_t any = 0;
 #pragma unroll
-            for (int i = 0; i < TQ; ++i)
-                if (ballot((w01[u] & msk[i]) == qm[i]) & live[u]) flagged |= 1ull << (u * TQ + i);
+            for (int u = 0; u < kScanUnroll; ++u) any |= ballot((w01[u] & msk[i]) == qm[i]);
+            if (any) flagged |= kTileBits << i;
         }
         // slow path, one flagged pair at a time (tiles in ascending order)
         while (flagged) {
@@ -302,6 +310,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
             const uint32_t* q = qwords + i * W;
             const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
             const bool cand = act && (w & st[i].msk) == st[i].qm;
+            if (ballot(cand) == 0) continue;  // another tile of this query had the candidate
             int lc = -1;
             if (cand) {
                 const uint64_t x = w ^ q01;
