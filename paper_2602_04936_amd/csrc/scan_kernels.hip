@@ -288,12 +288,19 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         // flagged query gets a bit for each of its tiles, and the slow path
         // skips tiles without a candidate.  Lanes past the chunk re-read its
         // last row, so they may flag a query; the slow path drops them.
+        // A filter that needs both words whole (the usual case once a limit
+        // asks for 64 bits or more) is a plain equality test.
         uint64_t flagged = 0;
 #pragma unroll
         for (int i = 0; i < TQ; ++i) {
             uint64_t any = 0;
+            if (msk[i] == ~0ull) {
 #pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) any |= ballot((w01[u] & msk[i]) == qm[i]);
+                for (int u = 0; u < kScanUnroll; ++u) any |= ballot(w01[u] == qm[i]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kScanUnroll; ++u) any |= ballot((w01[u] & msk[i]) == qm[i]);
+            }
             if (any) flagged |= kTileBits << i;
         }
         // slow path, one flagged pair at a time (tiles in ascending order)
