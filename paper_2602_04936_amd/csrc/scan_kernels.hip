@@ -99,8 +99,11 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const 
                 }
             }
         }
-        // one LDS add per distinct LCP value in the wave
-        uint64_t pending = ballot(act);
+        // rows sharing no token with the query (most of them) in one add,
+        // then one LDS add per distinct nonzero LCP value in the wave
+        const uint64_t zero = ballot(act && lc == 0);
+        if (lane == 0 && zero) atomicAdd(&h[0], (uint32_t)popc64(zero));
+        uint64_t pending = ballot(act && lc != 0);
         while (pending) {
             const int v = readlane_i(lc, low_lane(pending));
             const uint64_t same = ballot(((pending >> lane) & 1ull) && lc == v);
