@@ -132,6 +132,34 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
                              int32_t* out_ids, int32_t* out_lcp, void* stream);
 
 /*
+ * Allocation-free form of lcp_scan_topk_dev, for callers that cannot allocate
+ * device memory during a call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  The scan's working memory
+ * (partial top-k lists, per-query limits and fill counts, seed histograms,
+ * query key words) lives in one fixed array of LCP_NOALLOC_SCRATCH_BYTES that
+ * the library's device code holds on each GPU it runs on until the process
+ * ends; the call allocates nothing, creates no events and never synchronises.
+ * The first call on a device looks up that array's device address once.
+ *
+ * Arguments, output layout and answers are those of lcp_scan_topk_dev
+ * (bit-identical).  Additional limits:
+ *   Q : at most 262,140 per call, and small enough that the scratch holds the
+ *       partial lists: about Q * k_max * 16 bytes at the least, plus
+ *       Q * (L + W + 35) * 4 bytes, must fit in LCP_NOALLOC_SCRATCH_BYTES
+ *       (e.g. Q = 8,192 at k_max = 100 fits).  A larger batch is rejected with
+ *       LCP_EINVAL before anything is launched; split it into several calls.
+ * Concurrency: every call on one GPU shares that GPU's array (the previous
+ * call's contents are overwritten; the values that must start at zero are
+ * cleared by the call's first kernel).  Calls whose work overlaps on one GPU,
+ * on different streams or from different threads, race on the array and give
+ * unspecified answers: issue them on one stream, or order them with events.
+ */
+#define LCP_NOALLOC_SCRATCH_BYTES (32u << 20)
+lcp_status lcp_scan_topk_dev_noalloc(const lcp_index* index, const void* queries, int64_t Q,
+                                     const int32_t* k_dev, const int64_t* off_dev, int32_t k_max,
+                                     int32_t* out_ids, int32_t* out_lcp, void* stream);
+
+/*
  * Append n rows to an index; they get ids N, N+1, ..., N+n-1.  Afterwards the
  * index is identical (sorted order, adjacent LCP, answers) to one built over
  * the concatenated rows.  The paper lists dynamic insertion as future work

@@ -16,12 +16,13 @@ from typing import Optional, Sequence, Union
 import numpy as np
 import torch
 
-__all__ = ["Index", "TopK", "LcpError", "LIB_PATH", "K_MAX", "L_MAX", "lib"]
+__all__ = ["Index", "TopK", "LcpError", "LIB_PATH", "K_MAX", "L_MAX", "NOALLOC_SCRATCH_BYTES", "lib"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblcp.so")
 K_MAX = 1024
 L_MAX = 255
+NOALLOC_SCRATCH_BYTES = 32 << 20  # LCP_NOALLOC_SCRATCH_BYTES
 
 _STATUS = {0: "LCP_OK", -1: "LCP_EINVAL", -2: "LCP_ENOMEM", -3: "LCP_EDEVICE", -4: "LCP_ERANGE",
            -5: "LCP_ENOTIMPL"}
@@ -44,6 +45,7 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_scan_topk": [vp, vp, i64, vp, vp, vp, vp],
         "lcp_topk_dev": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
         "lcp_scan_topk_dev": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
+        "lcp_scan_topk_dev_noalloc": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
         "lcp_index_info": [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                            ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "lcp_index_views": [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)],
@@ -183,12 +185,16 @@ class Index:
         return self._run(lib.lcp_scan_topk, queries, k, stream, out)
 
     def topk_dev(self, queries: torch.Tensor, k_dev: torch.Tensor, off_dev: torch.Tensor, k_max: int,
-                 out_ids: torch.Tensor, out_lcp: torch.Tensor, stream=None, scan: bool = False):
-        """Device-k variant (lcp_topk_dev / lcp_scan_topk_dev): no host staging."""
+                 out_ids: torch.Tensor, out_lcp: torch.Tensor, stream=None, scan: bool = False,
+                 noalloc: bool = False):
+        """Device-k variant (lcp_topk_dev / lcp_scan_topk_dev): no host staging.  With scan=True and
+        noalloc=True: lcp_scan_topk_dev_noalloc (fixed scratch, no allocation)."""
         q = _token_tensor(queries, self.token_bytes)
         if k_dev.dtype != torch.int32 or off_dev.dtype != torch.int64:
             raise TypeError("k_dev must be int32 and off_dev int64")
-        fn = lib.lcp_scan_topk_dev if scan else lib.lcp_topk_dev
+        if noalloc and not scan:
+            raise ValueError("the allocation-free entry point is the full scan's (scan=True)")
+        fn = (lib.lcp_scan_topk_dev_noalloc if noalloc else lib.lcp_scan_topk_dev) if scan else lib.lcp_topk_dev
         _check(fn(self._h, q.data_ptr(), q.shape[0], k_dev.data_ptr(), off_dev.data_ptr(), int(k_max),
                   out_ids.data_ptr(), out_lcp.data_ptr(), _stream_handle(stream)))
 

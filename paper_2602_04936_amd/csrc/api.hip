@@ -304,6 +304,33 @@ lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int6
     return run_dev(idx, path, queries, Q, kbuf_k(c, Q), kbuf_off(c), 0, kmax, out_ids, out_lcp, s, c);
 }
 
+// Fixed scratch of the allocation-free full scan: one copy per device,
+// allocated with the library's device code and held until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host the name
+// only stands for the symbol): its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocScratchBytes = LCP_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint64_t scratch[kNoAllocScratchBytes / sizeof(uint64_t)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_ptr[kMaxDevices] = {};
+
+// caller has made `dev` current
+lcp_status scratch_on_device(int dev, uint64_t** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(LCP_EDEVICE, "device %d is beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LCP_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<uint64_t*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LCP_OK;
+}
+
 lcp_status query_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
                      const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp, void* stream) {
     lcp_status st = check_query_args(idx, queries, Q, out_ids, out_lcp);
@@ -556,6 +583,47 @@ lcp_status lcp_scan_topk_dev(const lcp_index* index, const void* queries, int64_
                              const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
                              void* stream) {
     return query_dev(index, Path::Scan, queries, Q, k_dev, off_dev, k_max, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_scan_topk_dev_noalloc(const lcp_index* idx, const void* queries, int64_t Q, const int32_t* k_dev,
+                                     const int64_t* off_dev, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
+                                     void* stream) {
+    lcp_status st = check_query_args(idx, queries, Q, out_ids, out_lcp);
+    if (st != LCP_OK) return st;
+    if (Q == 0) return LCP_OK;
+    if (!k_dev || !off_dev) return fail(LCP_EINVAL, "NULL k_dev or off_dev");
+    if (k_max < 1 || k_max > LCP_K_MAX) return fail(LCP_EINVAL, "k_max = %d is outside [1, %d]", k_max, LCP_K_MAX);
+    if (Q > kSliceScan)
+        return fail(LCP_EINVAL, "Q = %lld is above %lld, the largest batch of one allocation-free scan",
+                    (long long)Q, (long long)kSliceScan);
+    // everything but the partial lists, then the partial lists in what is left
+    const ScanPlan probe = plan_scan(idx->N, Q, k_max, 0);
+    const size_t fixed = scan_partial_entries(probe, Q, k_max, idx->g) * sizeof(uint64_t);
+    const int64_t left = fixed < kNoAllocScratchBytes ? (int64_t)(kNoAllocScratchBytes - fixed) : 0;
+    const ScanPlan plan = plan_scan(idx->N, Q, k_max, left);
+    if (plan.nparts == 0 ||
+        scan_partial_entries(plan, Q, k_max, idx->g) * sizeof(uint64_t) > kNoAllocScratchBytes)
+        return fail(LCP_EINVAL,
+                    "Q = %lld queries with k_max = %d need more than the %zu bytes of fixed scratch "
+                    "(at least %lld bytes); split the batch",
+                    (long long)Q, k_max, kNoAllocScratchBytes,
+                    (long long)(fixed + (size_t)Q * (size_t)k_max * 16));
+    HIP_TRY(hipSetDevice(idx->device));
+    uint64_t* ptr = nullptr;
+    st = scratch_on_device(idx->device, &ptr);
+    if (st != LCP_OK) return st;
+    QueryBatch qb;
+    qb.raw = queries;
+    qb.Q = Q;
+    qb.k = k_dev;
+    qb.off = off_dev;
+    qb.k_uniform = 0;
+    qb.q_base = 0;
+    qb.k_max = k_max;
+    qb.out_ids = out_ids;
+    qb.out_lcp = out_lcp;
+    HIP_TRY(launch_scan(idx->view(), qb, plan, ptr, static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr));
+    return LCP_OK;
 }
 
 lcp_status lcp_topk_persistent(const lcp_index* idx, const void* queries, int64_t q_capacity,

@@ -109,7 +109,11 @@ struct ScanPlan {
     int64_t seed_chunk_rows;
     int64_t chunk_rows;
 };
-ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max);
+// part_budget_bytes bounds the partial lists (Q * nparts * k_max * 8 bytes);
+// nparts == 0 in the result means not even one seed chunk and one row chunk
+// per query fit in it.
+constexpr int64_t kScanPartBudget = (int64_t)256 << 20;
+ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max, int64_t part_budget_bytes = kScanPartBudget);
 
 // Per-call scratch of the scan, carved from one device allocation.
 struct ScanScratch {

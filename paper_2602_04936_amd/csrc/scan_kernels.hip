@@ -514,7 +514,7 @@ static int tq_for(int nr, int64_t Q) {
 constexpr int64_t kChunkMinRows = 2048;
 constexpr int64_t kSeedRows = 65536;
 
-ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
+ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max, int64_t part_budget_bytes) {
     ScanPlan p;
     p.nr = nr_for(k_max);
     p.tq = tq_for(p.nr, Q);
@@ -530,7 +530,12 @@ ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max) {
     if (parts > seed_tiles) parts = seed_tiles;
     p.seed_parts = (int)(parts < 1 ? 1 : parts);
     const int64_t bytes_per_chunk = Q * (int64_t)k_max * 8;
-    const int64_t max_by_mem = bytes_per_chunk > 0 ? ((int64_t)256 << 20) / bytes_per_chunk : 1;
+    const int64_t max_by_mem = bytes_per_chunk > 0 ? part_budget_bytes / bytes_per_chunk : 1;
+    if (max_by_mem < 2) {  // one seed chunk and one row chunk per query do not fit
+        p.seed_chunks = p.chunks = p.nparts = 0;
+        p.seed_chunk_rows = p.chunk_rows = 0;
+        return p;
+    }
     // sampled rows: one-step chunks while the grid stays near 4096 blocks,
     // fewer and longer ones for many query groups or a tight partial budget
     int64_t sc = (p.seed_rows + kSeedChunkRows - 1) / kSeedChunkRows;
