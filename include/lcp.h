@@ -105,6 +105,25 @@ lcp_status lcp_topk(const lcp_index* index, const void* queries, int64_t Q, cons
                     int32_t* out_ids, int32_t* out_lcp, void* stream);
 
 /*
+ * lcp_topk that also reports, per query, the shape of the work the method did
+ * (the quantities section 6.2's range-scan cost is stated in, Theorem "Range
+ * Scan Complexity"): the answers are those of lcp_topk, and
+ *
+ *   stats : device int32 [Q][4], 16-byte aligned; query i gets
+ *           stats[4i + 0] = c, the cutoff LCP: the largest d with at least
+ *                           min(k, N) rows of LCP >= d,
+ *           stats[4i + 1] = n_gt, the rows with LCP > c (all in the answer),
+ *           stats[4i + 2] = the rows with LCP exactly c (the tied range the
+ *                           lowest ids are taken from),
+ *           stats[4i + 3] = the tie selection used: 0 none needed, 1 id walk
+ *                           (c = 0), 2 wave minima, 3 bisection on id bits,
+ *                           4 pruned by per-64-position minima, 5 sorted list.
+ * Errors: those of lcp_topk; LCP_EINVAL for a NULL or misaligned stats.
+ */
+lcp_status lcp_topk_stats(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,
+                          int32_t* out_ids, int32_t* out_lcp, int32_t* stats, void* stream);
+
+/*
  * Plain path: the same answer as lcp_topk computed by brute force (LCP of every
  * query against all N rows, then per-query top-k; the "full scan" the paper
  * compares against in section 7, Table "TAL range-scan vs full-scan").

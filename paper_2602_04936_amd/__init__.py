@@ -43,6 +43,7 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_index_build": [vp, i64, i32, i32, vp, ctypes.POINTER(vp)],
         "lcp_topk": [vp, vp, i64, vp, vp, vp, vp],
         "lcp_scan_topk": [vp, vp, i64, vp, vp, vp, vp],
+        "lcp_topk_stats": [vp, vp, i64, vp, vp, vp, vp, vp],
         "lcp_topk_dev": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
         "lcp_scan_topk_dev": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
         "lcp_scan_topk_dev_noalloc": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
@@ -179,6 +180,23 @@ class Index:
     def topk(self, queries, k: Union[int, Sequence[int], np.ndarray], stream=None, out=None) -> TopK:
         """Index path (lcp_topk)."""
         return self._run(lib.lcp_topk, queries, k, stream, out)
+
+    def topk_stats(self, queries, k: Union[int, Sequence[int], np.ndarray], stream=None, out=None):
+        """Index path with per-query work shape (lcp_topk_stats): returns (TopK, stats) where stats is
+        an int32 [Q, 4] device tensor of (cutoff LCP c, rows above c, rows tied at c, tie selection)."""
+        q, kk, off = self._prep(queries, k)
+        total = int(off[-1])
+        if out is None:
+            ids = torch.empty(total, dtype=torch.int32, device=self.device)
+            lcps = torch.empty(total, dtype=torch.int32, device=self.device)
+        else:
+            ids, lcps = out
+            if ids.numel() < total or lcps.numel() < total:
+                raise ValueError("output tensors are too small")
+        stats = torch.empty((q.shape[0], 4), dtype=torch.int32, device=self.device)
+        _check(lib.lcp_topk_stats(self._h, q.data_ptr(), q.shape[0], kk.ctypes.data, ids.data_ptr(),
+                                  lcps.data_ptr(), stats.data_ptr(), _stream_handle(stream)))
+        return TopK(ids, lcps, off), stats
 
     def scan_topk(self, queries, k: Union[int, Sequence[int], np.ndarray], stream=None, out=None) -> TopK:
         """Plain full-scan path (lcp_scan_topk)."""

@@ -228,7 +228,7 @@ constexpr int64_t kSliceScan = 65535 * 4;
 
 lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
                    const int64_t* off_dev, int32_t k_uniform, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
-                   hipStream_t s, StreamCtx* c) {
+                   hipStream_t s, StreamCtx* c, int32_t* stats = nullptr) {
     HIP_TRY(hipSetDevice(idx->device));
     const IndexView ix = idx->view();
     const size_t row_bytes = (size_t)idx->L * idx->g.tb;
@@ -244,6 +244,7 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
         qb.k_max = k_max;
         qb.out_ids = out_ids;  // offsets are absolute
         qb.out_lcp = out_lcp;
+        qb.stats = stats ? stats + 4 * q0 : nullptr;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
         if (idx->timing) {
             int need = path == Path::Index ? 2 : 3;
@@ -272,7 +273,7 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
 }
 
 lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k,
-                      int32_t* out_ids, int32_t* out_lcp, void* stream) {
+                      int32_t* out_ids, int32_t* out_lcp, void* stream, int32_t* stats = nullptr) {
     lcp_status st = check_query_args(idx, queries, Q, out_ids, out_lcp);
     if (st != LCP_OK) return st;
     if (Q == 0) return LCP_OK;
@@ -298,10 +299,10 @@ lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int6
                 return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
     }
     if (diff == 0)  // one k for all: offsets are i * k, nothing to copy
-        return run_dev(idx, path, queries, Q, nullptr, nullptr, k[0], kmax, out_ids, out_lcp, s, c);
+        return run_dev(idx, path, queries, Q, nullptr, nullptr, k[0], kmax, out_ids, out_lcp, s, c, stats);
     st = stage_k(c, Q, k);
     if (st != LCP_OK) return st;
-    return run_dev(idx, path, queries, Q, kbuf_k(c, Q), kbuf_off(c), 0, kmax, out_ids, out_lcp, s, c);
+    return run_dev(idx, path, queries, Q, kbuf_k(c, Q), kbuf_off(c), 0, kmax, out_ids, out_lcp, s, c, stats);
 }
 
 // Fixed scratch of the allocation-free full scan: one copy per device,
@@ -567,6 +568,13 @@ lcp_status lcp_index_build(const void* tokens, int64_t N, int32_t L, int32_t V, 
 lcp_status lcp_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k, int32_t* out_ids,
                     int32_t* out_lcp, void* stream) {
     return query_host(index, Path::Index, queries, Q, k, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_topk_stats(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,
+                          int32_t* out_ids, int32_t* out_lcp, int32_t* stats, void* stream) {
+    if (Q > 0 && !stats) return fail(LCP_EINVAL, "stats is NULL");
+    if (reinterpret_cast<uintptr_t>(stats) % 16 != 0) return fail(LCP_EINVAL, "stats is not 16-byte aligned");
+    return query_host(index, Path::Index, queries, Q, k, out_ids, out_lcp, stream, stats);
 }
 
 lcp_status lcp_scan_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,

@@ -79,6 +79,19 @@ struct QueryBatch {
     int32_t k_max;
     int32_t* out_ids;
     int32_t* out_lcp;
+    // index path only, optional: per query of this batch, 4 int32 at stats + 4 * i:
+    // cutoff c, inner-group rows n_gt = |G_{c+1}|, tied rows |G_c| - n_gt, and
+    // which tie selection ran (a TiePath value)
+    int32_t* stats = nullptr;
+};
+
+enum TiePath : int32_t {
+    kTieNone = 0,    // the inner group fills the answer (no tied rows taken)
+    kTieIdWalk = 1,  // c = 0: ids walked in ascending order
+    kTieFew = 2,     // at most 16 ids from at most 512 tied rows: wave minima
+    kTieSelect = 3,  // at most 256 ids from at most 512 tied rows: bisection on id bits
+    kTiePruned = 4,  // long range: pruned by the per-64-position id minima
+    kTieList = 5     // the sorted list over every tied row
 };
 
 __device__ __forceinline__ int query_k(const QueryBatch& qb, int64_t qi) {

@@ -560,6 +560,17 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
         }
     }
 
+    if (qb.stats != nullptr) {
+        const bool pruned = m <= kSelMax && (in_lo - l) + (r - in_hi) >= kWave * 4 * (m > 8 ? m : 8);
+        const int path = m <= 0            ? kTieNone
+                         : c == 0          ? kTieIdWalk
+                         : held && m <= kFewTied ? kTieFew
+                         : held            ? kTieSelect
+                         : pruned          ? kTiePruned
+                                           : kTieList;
+        if (lane == 0) *reinterpret_cast<int4*>(qb.stats + 4 * qi) = make_int4(c, n_gt, tn, path);
+    }
+
     // ---- 4. the m lowest ids among rows with LCP exactly c
     if (m > 0) {
         if (c == 0) {
@@ -657,9 +668,10 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     }
 }
 
-// Small lists: registers are capped so that 8 waves fit per SIMD and a whole
-// 8,192-query batch is resident at once.  Large lists (k > 256) keep their
-// registers instead.
+// Registers: with one list register (k <= 64) the cap lets 8 waves fit per
+// SIMD, so a whole 8,192-query batch is resident at once; two or four list
+// registers (k <= 256) would spill under that cap, so those variants allow 6
+// waves per SIMD instead.  Large lists (k > 256) keep their registers.
 template <int NR, int VEC>
 __device__ __forceinline__ void one_query_per_wave(const IndexView& ix, const QueryBatch& qb) {
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -692,9 +704,11 @@ __device__ __forceinline__ void queries_from_counter(const IndexView& ix, const 
     }
 }
 
+constexpr int waves_per_simd(int nr) { return nr == 1 ? 8 : 6; }
+
 template <int NR, int VEC>
-__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_index_query(
-    IndexView ix, QueryBatch qb) {
+__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(waves_per_simd(NR), 8))) void
+k_index_query(IndexView ix, QueryBatch qb) {
     one_query_per_wave<NR, VEC>(ix, qb);
 }
 
@@ -704,7 +718,7 @@ __global__ __launch_bounds__(kQueryWaves * kWave) void k_index_query_wide(IndexV
 }
 
 template <int NR, int VEC>
-__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_index_query_persistent(
+__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_index_query_persistent(
     IndexView ix, QueryBatch qb, const int64_t* q_count, unsigned long long* counter) {
     queries_from_counter<NR, VEC>(ix, qb, q_count, counter);
 }
@@ -712,8 +726,8 @@ __global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_pe
 // One wave per query of the capacity; waves past the device-side batch size
 // leave at once.
 template <int NR, int VEC>
-__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_index_query_counted(
-    IndexView ix, QueryBatch qb, const int64_t* q_count) {
+__global__ __launch_bounds__(kQueryWaves * kWave) __attribute__((amdgpu_waves_per_eu(waves_per_simd(NR), 8))) void
+k_index_query_counted(IndexView ix, QueryBatch qb, const int64_t* q_count) {
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int64_t qi = (int64_t)blockIdx.x * kQueryWaves + wv;
     if (qi < *q_count) index_query_body<NR, VEC>(ix, qb, qi);

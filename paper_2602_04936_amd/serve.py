@@ -351,7 +351,7 @@ def run_synchronous(index, requests: List[Request], scan: bool = True, max_wall_
 
 
 def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0, append=None,
-                    max_wall_s: float = 120.0) -> dict:
+                    max_wall_s: float = 120.0, keep=None) -> dict:
     """Paced stream of query batches (the GNC loop of section 7, Table "GNC
     benchmark": each step queries the current readings of every sensor).
 
@@ -360,6 +360,10 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
     append_every : every that many steps, `append(index, batch)` is called with
                    the step's batch and must return the index to use next
                    (rows join the database with the next ids)
+    keep         : optional predicate on the step number; the answers of the
+                   steps it accepts are returned under "answers" as
+                   {t: (ids [S, k], lcps [S, k])} (copied after the step's
+                   latency is taken)
     Returns the achieved step rate and step latency percentiles (latency =
     completion - release time, so a late step also delays the next ones).
     """
@@ -367,6 +371,7 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
     dev = index.device
     lat = []
     appends_ms = []
+    kept = {}
     buf = {}
     t0 = time.perf_counter()
     n = 0
@@ -393,6 +398,8 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
         done = time.perf_counter() - t0
         lat.append((done - release) * 1e3)
         n += 1
+        if keep is not None and keep(t):
+            kept[t] = (buf["ids_h"].numpy().reshape(-1, k).copy(), buf["lcp_h"].numpy().reshape(-1, k).copy())
         if append_every and append is not None and (t + 1) % append_every == 0:
             a0 = time.perf_counter()
             index = append(index, batch)
@@ -412,4 +419,5 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
         "appends": len(appends_ms),
         "append_ms_mean": round(float(np.mean(appends_ms)), 3) if appends_ms else None,
         "index": index,
+        **({"answers": kept} if keep is not None else {}),
     }
