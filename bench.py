@@ -119,17 +119,47 @@ def main():
     dt_single = timed_steps(1)
     dt = timed_steps(nstreams)
     same_outputs = all(torch.equal(o[0], ids) and torch.equal(o[1], lcps) for o in outs[1:])
-    # kernel duration from HIP events on the library's stream, in a second pass
-    # of the same steps so that the events do not sit inside the timed region
-    idx.set_kernel_timing(True)
-    idx.kernel_time(0)
+
+    def event_blocks(n_str, blocks=5):
+        """GPU time of `blocks` further blocks of --steps steps each, from an
+        event on the first stream that the others wait on, to an event there
+        recorded after it waits for the others' last steps."""
+        times = []
+        for _ in range(blocks):
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(streams[0])
+            for j in range(1, n_str):
+                streams[j].wait_event(a)
+            for i in range(args.steps):
+                idx.topk(q_dev, args.k, out=outs[i % n_str], stream=streams[i % n_str])
+            for j in range(1, n_str):
+                e = torch.cuda.Event()
+                e.record(streams[j])
+                streams[0].wait_event(e)
+            b.record(streams[0])
+            b.synchronize()
+            times.append(a.elapsed_time(b) / args.steps)
+        return times
+
+    blocks_multi = event_blocks(nstreams)
+    blocks_single = event_blocks(1)
+    # kernel duration: K launches back to back on one stream, between two HIP
+    # events on that stream (the kernel runs on the stream it is given), in a
+    # pass of its own so that the events do not sit inside the timed region
+    s0 = streams[0]
+    idx.topk(q_dev, args.k, out=outs[0], stream=s0)
+    torch.cuda.synchronize()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ea.record(s0)
     for _ in range(args.steps):
-        idx.topk(q_dev, ks, out=(ids, lcps))
-    kms, kn = idx.kernel_time(0)
-    idx.set_kernel_timing(False)
+        idx.topk(q_dev, args.k, out=outs[0], stream=s0)
+    eb.record(s0)
+    eb.synchronize()
+    k_avg_ms = ea.elapsed_time(eb) / args.steps
     ms_per_step = dt * 1e3 / args.steps
     qps = w.Q * args.steps / dt
-    k_avg_ms = kms / max(kn, 1)
+    kn = args.steps
     log(args, f"[bench] index path: {ms_per_step:.4f} ms/step, {qps / 1e6:.2f} M queries/s on {nstreams} streams "
               f"({dt_single * 1e3 / args.steps:.4f} ms/step on one), kernel {k_avg_ms * 1e3:.1f} us avg over {kn}")
     got_ids = ids.cpu().numpy()
@@ -243,28 +273,26 @@ def main():
         del wl, lq, lo
         log(args, f"[bench] larger than the Infinity Cache: {large}")
 
-    # ---- parity spot check against the CPU oracle (outside every timed region)
+    # ---- parity of the whole bench batch against the CPU oracle (outside every timed region)
     parity = None
     try:
         import oracle
-        sample = np.arange(0, w.Q, max(1, w.Q // 64))
-        wi, wl, woff = oracle.c_topk(w.db, w.queries[sample], ks[sample])
-        ok = True
-        off = np.concatenate([[0], np.cumsum(ks)])
-        for j, qi in enumerate(sample):
-            a, b = off[qi], off[qi + 1]
-            ok &= bool((got_ids[a:b] == wi[woff[j]:woff[j + 1]]).all() and
-                       (got_lcp[a:b] == wl[woff[j]:woff[j + 1]]).all())
-        parity = {"queries_checked": int(len(sample)), "bit_exact": ok}
+        wi, wl, _ = oracle.c_topk(w.db, w.queries, ks)
+        parity = {"queries_checked": int(w.Q), "bit_exact": bool((got_ids == wi).all() and (got_lcp == wl).all())}
     except Exception as e:  # the oracle is a test dependency; report, do not fail the bench
         parity = {"error": repr(e)}
 
-    # ---- roofline of the index-path kernel: the bytes a comparison-based search
-    # must move per query (query row + ceil(log2(N+1)) probed rows), plus the
-    # perm id and adjacent-LCP byte of each answer and the 8-byte output entry
+    # ---- roofline of the index-path kernel.  Algorithmic bytes per query: the
+    # query row, the ceil(log2(N+1)) rows a comparison search must probe, one A
+    # byte per row of the cutoff group G_c plus its two boundaries, one perm id
+    # per row above or tied at the cutoff (the range scan's items), 8 bytes per
+    # output entry.  The per-query counts come from the kernel itself.
     probes = int(np.ceil(np.log2(w.N + 1)))
-    bytes_per_query = row_bytes + probes * row_bytes + args.k * (4 + 1) + args.k * 8
-    idx_bytes = bytes_per_query * w.Q
+    _, st = idx.topk_stats(q_dev, args.k)
+    torch.cuda.synchronize()
+    shape = work_shape(st.cpu().numpy(), w.N, args.k, row_bytes, probes)
+    bytes_per_query = shape.pop("algorithmic_bytes_per_query")
+    idx_bytes = shape.pop("algorithmic_bytes_per_launch")
     idx_gbs = idx_bytes / (k_avg_ms * 1e-3) / 1e9
     scan_kernel_ms = s_ms / max(s_n, 1)
     passes = idx.scan_info(w.Q, args.k)[0]
@@ -290,6 +318,7 @@ def main():
             t, b, kk = synth.serving_schedule(rate, args.serve_seconds, seed=1004, k_mode="uniform")
             reqs = serve.requests_from_schedule(w.queries, t, b, kk)
             rep = serve.run_served(idx, reqs)
+            rep.update(served_check(idx, reqs, w.db))
             serving.setdefault("index_continuous_batching_k_uniform_1_100", {})[str(int(rate))] = rep
             log(args, f"[bench] served index path, k uniform 1..100 @{int(rate)}/s: {rep}")
 
@@ -449,23 +478,34 @@ def main():
         "vs_baseline": None,
         "dtype": "u16",
         "data": "synthetic",
+        "inputs_sha256": {"db": synth.sha256_of(w.db), "queries": synth.sha256_of(w.queries),
+                          "numpy": np.__version__},
         "config": {"workload": "c3 hierarchy: N=2,000,000 L=32 uint16 V=4096, Q=8192 per step, k=10",
                    "N": w.N, "L": w.L, "V": w.V, "queries_per_step": w.Q, "k": args.k,
                    "path": "index (lcp_topk)", "parallelism": "single GPU",
                    "streams": nstreams},
         "single_stream": {"ms_per_step": round(dt_single * 1e3 / args.steps, 5),
                           "value": round(w.Q * args.steps / dt_single, 1)},
+        "event_timed_blocks": {
+            "blocks": len(blocks_multi), "steps_per_block": args.steps,
+            "ms_per_step": [round(x, 5) for x in blocks_multi],
+            "median_value": round(w.Q / (float(np.median(blocks_multi)) * 1e-3), 1),
+            "single_stream_ms_per_step": [round(x, 5) for x in blocks_single],
+            "single_stream_median_value": round(w.Q / (float(np.median(blocks_single)) * 1e-3), 1)},
         "streams_outputs_identical": same_outputs,
         "roofline": {"kernel": "k_index_query", "bound": "hbm", "achieved": round(idx_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(idx_gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(w.Q, args.k), "traffic_unit": "bytes per launch",
-                     "avg_kernel_us": round(k_avg_ms * 1e3, 2),
-                     "algorithmic_bytes_per_query": bytes_per_query},
+                     "avg_kernel_us": round(k_avg_ms * 1e3, 2), "launches_timed": kn,
+                     "algorithmic_bytes_per_query": round(bytes_per_query, 1),
+                     "algorithmic_bytes_per_launch": int(idx_bytes),
+                     "traffic_over_algorithmic": (round(measured_traffic(w.Q, args.k) / idx_bytes, 3)
+                                                  if measured_traffic(w.Q, args.k) else None)},
+        "work_shape": shape,
         "scan": {"qps": round(scan_qps, 1), "ms_per_batch": round(sdt * 1e3 / args.scan_steps, 4),
                  "index_speedup": round(qps / scan_qps, 2), "scan_kernel_ms": round(scan_kernel_ms, 4),
                  "merge_kernel_ms": round(m_ms / max(m_n, 1), 4), "passes_over_db": passes,
                  "plane_GBps": round(scan_bytes / (scan_kernel_ms * 1e-3) / 1e9, 1),
-                 "row_equivalent_GBps": round(w.N * row_bytes * passes / (scan_kernel_ms * 1e-3) / 1e9, 1),
                  "pair_lcp_per_s": round(w.Q * w.N / (scan_kernel_ms * 1e-3), 1),
                  "paths_bit_identical": paths_agree},
         "scan_roofline": {"kernel": "k_scan", "bound": "hbm", "queries": nbw, "passes_over_db": passes_bw,
@@ -511,6 +551,65 @@ def measured_traffic(queries, k):
     return int(m.group(1)) if h.hexdigest() == m.group(4) else None
 
 
+TIE_PATHS = ("none", "id_walk", "wave_minima", "bisection", "pruned", "sorted_list")
+
+
+def work_shape(st, N, k, row_bytes, probes):
+    """Per-query work of the index path from lcp_topk_stats rows (c, n_gt,
+    tied, tie path): histograms, and the algorithmic bytes per query,
+        R + ceil(log2(N+1)) R + (|G_c| + 2) + 4 (n_gt + |tied|) + 8 k,
+    with |G_c| = n_gt + |tied|.  At c = 0 the method walks ids instead of the
+    tied range (at most k' + 64 probes, no A bytes beyond the inner group), so
+    those queries are charged that walk."""
+    c, ngt, tied, path = (st[:, i].astype(np.int64) for i in range(4))
+    kp = min(k, N)
+    walk = c == 0
+    a_bytes = np.where(walk, ngt + 2, ngt + tied + 2)
+    ids_read = np.where(walk, ngt + np.minimum(tied, kp - ngt + 64), ngt + tied)
+    per_q = row_bytes + probes * row_bytes + a_bytes + 4 * ids_read + 8 * k
+    edges = [0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 31]
+    return {
+        "queries": int(st.shape[0]),
+        "c_counts": {str(v): int(n) for v, n in enumerate(np.bincount(c)) if n},
+        "n_gt_mean": round(float(ngt.mean()), 2),
+        "tied_mean": round(float(tied.mean()), 2),
+        "tied_percentiles": {p: int(np.percentile(tied, int(p))) for p in ("50", "90", "99")},
+        "tied_max": int(tied.max()),
+        "tied_histogram": {"edges": edges, "counts": np.histogram(tied, bins=edges)[0].tolist()},
+        "G_c_mean": round(float((ngt + tied).mean()), 2),
+        "tie_path_counts": {TIE_PATHS[i]: int(n) for i, n in enumerate(np.bincount(path, minlength=6)) if n},
+        "algorithmic_bytes_per_query": float(per_q.mean()),
+        "algorithmic_bytes_per_launch": int(per_q.sum()),
+    }
+
+
+def served_check(idx, reqs, db, n_oracle=40):
+    """Served answers (k uniform on [1, 100]) against the same requests answered
+    in one eager batch, and a spread sample of requests against the C oracle."""
+    import torch
+    qs = np.concatenate([r.queries for r in reqs])
+    ks = np.concatenate([np.full(r.b, r.k, np.int32) for r in reqs])
+    res = idx.topk(qs, ks)
+    torch.cuda.synchronize()
+    bi, bl = res.ids.cpu().numpy(), res.lcps.cpu().numpy()
+    got_i = np.concatenate([r.ids.reshape(-1) for r in reqs])
+    got_l = np.concatenate([r.lcps.reshape(-1) for r in reqs])
+    out = {"results_match_batch_run": bool((got_i == bi).all() and (got_l == bl).all())}
+    try:
+        import oracle
+        pick = sorted(set(np.linspace(0, len(reqs) - 1, min(n_oracle, len(reqs))).astype(int).tolist()))
+        sq = np.concatenate([reqs[i].queries for i in pick])
+        sk = np.concatenate([np.full(reqs[i].b, reqs[i].k, np.int32) for i in pick])
+        wi, wl, _ = oracle.c_topk(db, sq, sk)
+        gi = np.concatenate([reqs[i].ids.reshape(-1) for i in pick])
+        gl = np.concatenate([reqs[i].lcps.reshape(-1) for i in pick])
+        out["oracle_checked_requests"] = len(pick)
+        out["oracle_bit_exact"] = bool((gi == wi).all() and (gl == wl).all())
+    except Exception as e:  # the oracle is a test dependency; report, do not fail the bench
+        out["oracle_error"] = repr(e)
+    return out
+
+
 def served_match(reqs, ref, Q):
     """Every served answer equals the same query's answer in the batch run."""
     ref_ids, ref_lcp = ref
@@ -529,29 +628,49 @@ def cpu_baseline(w, ks, args):
     import numpy as np
 
     import oracle
-    threads = oracle.threads(0)
-    # calibrate on a small slice, then run a sample sized to about --cpu-seconds
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    threads = int(oracle.native_lib().oracle_threads(0))
+    # calibrate on a small slice, then run a sample sized to about --cpu-seconds;
+    # the reported rate is the median of three runs of that sample
     probe = 64
     t = time.perf_counter()
-    oracle.c_topk(w.db, w.queries[:probe], ks[:probe])
+    oracle.c_topk(w.db, w.queries[:probe], ks[:probe], native=True)
     per_q = (time.perf_counter() - t) / probe
-    n = int(min(w.Q, max(probe, args.cpu_seconds / max(per_q, 1e-9))))
+    n = int(min(w.Q, max(probe, args.cpu_seconds / 3 / max(per_q, 1e-9))))
     sel = np.arange(n)
-    t = time.perf_counter()
-    oracle.c_topk(w.db, w.queries[sel], ks[sel])
-    el = time.perf_counter() - t
-    model = "unknown CPU"
+    runs = []
+    for _ in range(3):
+        t = time.perf_counter()
+        oracle.c_topk(w.db, w.queries[sel], ks[sel], native=True)
+        runs.append(time.perf_counter() - t)
+    el = float(np.median(runs))
+    return {"value": round(n / el, 2), "unit": "queries/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"first {n} of the {w.Q} bench queries against all N={w.N} rows, k={args.k}, "
+                      f"C brute force (oracle/cpu_topk.c built -O3 -march=native on this host, OpenMP over "
+                      f"queries, OMP_PROC_BIND={os.environ.get('OMP_PROC_BIND')}), median of 3 runs "
+                      f"({', '.join(f'{x:.2f}' for x in runs)} s)"}
+
+
+def cpu_model():
+    """Host processor as /proc/cpuinfo and the scheduler describe it."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                if ":" in line:
+                    key, val = (x.strip() for x in line.split(":", 1))
+                    if key in ("model name", "cpu family", "model", "stepping", "cpu MHz") and key not in info:
+                        info[key] = val
+                    if key == "flags" and "flags" not in info:
+                        info["flags"] = " ".join(x for x in val.split() if x in ("avx2", "avx512f", "avx512bw"))
     except OSError:
         pass
-    return {"value": round(n / el, 2), "unit": "queries/s", "cores": threads, "kind": "oracle", "cpu": model,
-            "sample": f"first {n} of the {w.Q} bench queries against all N={w.N} rows, k={args.k}, "
-                      f"C brute force (oracle/cpu_topk.c, OpenMP over queries), {el:.1f} s wall"}
+    info["logical_cpus_visible"] = os.cpu_count()
+    try:
+        info["cpus_allowed"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    return info
 
 
 if __name__ == "__main__":

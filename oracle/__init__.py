@@ -35,19 +35,40 @@ def build(verbose: bool = False) -> str:
     return _LIB
 
 
+def _bind(lib):
+    lib.oracle_topk.restype = ctypes.c_int
+    lib.oracle_topk.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_threads.argtypes = [ctypes.c_int32]
+    return lib
+
+
+_native = None
+
+
+def native_lib():
+    """The same C source compiled for the host it runs on (-O3 -march=native),
+    into a temporary directory (never shipped to another machine); used for the
+    CPU-baseline timing.  Returns the loaded library."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="cpu_topk_native_")
+        out = os.path.join(d, "libcpu_topk_native.so")
+        subprocess.run(["gcc", "-O3", "-march=native", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", out],
+                       check=True)
+        _native = _bind(ctypes.CDLL(out))
+    return _native
+
+
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(_LIB)
-        lib.oracle_topk.restype = ctypes.c_int
-        lib.oracle_topk.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
-                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
-        lib.oracle_threads.restype = ctypes.c_int
-        lib.oracle_threads.argtypes = [ctypes.c_int32]
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
 
 
@@ -55,9 +76,10 @@ def threads(nthreads: int = 0) -> int:
     return int(_load().oracle_threads(nthreads))
 
 
-def c_topk(db: np.ndarray, queries: np.ndarray, ks, nthreads: int = 0):
-    """Brute-force top-k for a batch (C oracle).  Returns (ids, lcps, offsets)."""
-    lib = _load()
+def c_topk(db: np.ndarray, queries: np.ndarray, ks, nthreads: int = 0, native: bool = False):
+    """Brute-force top-k for a batch (C oracle).  Returns (ids, lcps, offsets).
+    native=True runs the build made for this host (native_lib)."""
+    lib = native_lib() if native else _load()
     db = np.ascontiguousarray(db)
     queries = np.ascontiguousarray(queries, dtype=db.dtype)
     if db.dtype not in (np.uint8, np.uint16):
