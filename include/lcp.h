@@ -62,12 +62,15 @@ typedef enum {
  * Build an index over N rows (section 5.2, the sorted-order equivalent of
  * Algorithms 1-2: leaf order of the trie with posting lists in id order).
  * Besides the sorted rows, their ids and the adjacent-LCP array the index
- * keeps the top levels of a 65-ary search tree over the sorted rows, for
+ * keeps the top levels of a 65-ary search tree over the sorted rows, the
+ * sorted position where each first-token value starts, for
  * every run of 64 sorted positions the smallest id in it (used to skip most
  * of a long run of rows tied at the cutoff LCP), and the first 8 bytes of
  * every row in id order (the stream the full scan reads).  Device memory:
  * about N * (8 * row_words + 13.06) bytes plus at most 4.4 MB of search
- * tables.
+ * tables and 4 * (V + 2) bytes of directory; the first lcp_index_append adds a
+ * second copy of the order-dependent arrays (N * (4 * row_words + 5.06) bytes
+ * and the tables), with room for a quarter more rows.
  *
  *   tokens : device, [N][L] uint8 (V <= 256) or uint16 (V > 256).  The
  *            index copies them; the caller may free `tokens` after return.
@@ -183,16 +186,26 @@ lcp_status lcp_scan_topk_dev_noalloc(const lcp_index* index, const void* queries
  * index is identical (sorted order, adjacent LCP, answers) to one built over
  * the concatenated rows.  The paper lists dynamic insertion as future work
  * (section "Limitations"); this is the sorted-order merge: the new rows are
- * sorted, placed after equal old rows (their ids are larger), and the
- * adjacent-LCP array and search tables are recomputed.
+ * sorted, merged into the sorted order after equal old rows (their ids are
+ * larger), the adjacent LCP of old rows is carried over and recomputed only
+ * where a new row was inserted, and the search tables and tie summaries are
+ * rebuilt for the merged order.  The index keeps two copies of the sorted
+ * arrays: the merge writes the copy queries do not read, which becomes the
+ * one they read only when every step has succeeded, so on any error the index
+ * is unchanged.  Buffers grow with room for a quarter more rows; an append
+ * that fits allocates nothing, except the first one and appends of more than
+ * 8,192 rows (whose temporaries are allocated per call).
  *
  *   tokens : device, [n][L], same width as the index; every token < V.
  *   n      : 0 <= n, N + n <= 2^31 - 2^16 (n = 0 is a no-op).
  *   stream : the call first synchronises every stream the index has been used
  *            on, then runs on `stream` and synchronises it before returning.
  *            No query may run on the index during the call.
- * Errors: LCP_EINVAL, LCP_ERANGE (a token >= V; the index is unchanged),
- * LCP_ENOMEM, LCP_EDEVICE.
+ * A successful append moves the arrays queries read and changes N, so a HIP
+ * graph captured before it (lcp_topk_persistent) must not be replayed after
+ * it: compare lcp_index_generation before replaying.
+ * Errors: LCP_EINVAL, LCP_ERANGE (a token >= V), LCP_ENOMEM, LCP_EDEVICE; the
+ * index is unchanged after any of them.
  */
 lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, void* stream);
 
@@ -217,10 +230,37 @@ lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, voi
  *                 work counter; fewer blocks make waves loop over queries.
  * Capture: make one call on the stream first (it sets up the stream's work
  * counter); the call itself then allocates nothing and never synchronises.
+ * A graph captured from this call holds the index's arrays and N as they were
+ * at capture: after lcp_index_append it must be captured again (see
+ * lcp_index_generation).
  */
 lcp_status lcp_topk_persistent(const lcp_index* index, const void* queries, int64_t q_capacity,
                                const int64_t* q_count_dev, const int32_t* k_dev, const int64_t* off_dev,
                                int32_t k_max, int32_t* out_ids, int32_t* out_lcp, int32_t blocks, void* stream);
+
+/*
+ * Number of changes to what queries read since the build (0 after it): each
+ * successful lcp_index_append and each lcp_index_set_search that switches the
+ * mode adds one.  A HIP graph captured while it had one value must not be
+ * replayed once it has another.  Errors: LCP_EINVAL for a NULL argument.
+ */
+lcp_status lcp_index_generation(const lcp_index* index, uint64_t* generation);
+
+/*
+ * How the index path finds a query's insertion point (both give the same
+ * answers; this only changes the work):
+ *   mode 0 (default): a static 65-ary search whose top three levels come from
+ *          the search tables (each step compares the query with 64 pivots'
+ *          first 16 bytes in one coalesced load).
+ *   mode 1: the first-token directory, a table of V + 2 sorted positions
+ *          giving the range of rows that share the query's first token (the
+ *          prefix bucket of depth one, section 6.2, Definitions "Prefix
+ *          Bucket" and "Thermal-Aware Logic"); the 65-ary search then runs
+ *          over that range on the rows themselves.
+ * The call synchronises every stream the index has been used on.
+ * Errors: LCP_EINVAL (NULL index, mode not 0 or 1), LCP_EDEVICE.
+ */
+lcp_status lcp_index_set_search(lcp_index* index, int32_t mode);
 
 /* Synchronise every stream the index has been used on, then free it.  NULL is a no-op. */
 void lcp_index_free(lcp_index* index);

@@ -53,6 +53,8 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_scan_info": [vp, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)],
         "lcp_index_append": [vp, vp, i64, vp],
         "lcp_topk_persistent": [vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, vp],
+        "lcp_index_generation": [vp, ctypes.POINTER(ctypes.c_uint64)],
+        "lcp_index_set_search": [vp, i32],
         "lcp_set_kernel_timing": [vp, i32],
         "lcp_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -242,6 +244,17 @@ class Index:
         n = ctypes.c_int64()
         _check(lib.lcp_index_info(self._h, ctypes.byref(n), None, None, None, None))
         self.N = n.value
+
+    def set_search(self, mode: int):
+        """Insertion-point search of the index path (lcp_index_set_search): 0 = 65-ary search tables,
+        1 = first-token directory.  Answers are the same either way."""
+        _check(lib.lcp_index_set_search(self._h, int(mode)))
+
+    def generation(self) -> int:
+        """Changes of what queries read (lcp_index_generation); graphs captured at another value are stale."""
+        g = ctypes.c_uint64()
+        _check(lib.lcp_index_generation(self._h, ctypes.byref(g)))
+        return g.value
 
     # ------------------------------------------------------------- tooling
     def views(self):

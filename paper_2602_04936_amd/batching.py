@@ -36,7 +36,9 @@ class CapturedLaunch:
 
     cap_queries : largest batch; k_max : largest k any batch may use;
     blocks : 0 for one wave per query of the capacity, else a persistent grid.
-    The object owns its stream; replays run on that stream in order.  Per-batch
+    The object owns its stream; replays run on that stream in order.  The graph
+    holds the index's arrays as they were at capture, so `run` refuses to
+    replay it once the index has been appended to (its generation changed).  Per-batch
     k, offsets and size go up in one copy from one of two pinned staging
     buffers, so the host fills the next batch while the previous one runs.
     """
@@ -68,6 +70,7 @@ class CapturedLaunch:
             self._launch()
         self.stream.synchronize()
         self.graph = torch.cuda.CUDAGraph()
+        self.generation = index.generation()  # the index's arrays are baked into the graph
         with torch.cuda.graph(self.graph, stream=self.stream):
             self._launch()
         self.stream.synchronize()
@@ -80,12 +83,52 @@ class CapturedLaunch:
         self.index.topk_persistent(self.q, self.count, self.k, self.off, self.k_max, self.ids, self.lcps,
                                    blocks=self.blocks, stream=self.stream)
 
+    def stage(self, k, n: int) -> np.ndarray:
+        """Put a batch's size, offsets and k into the device buffers ahead of a
+        replay (for producers that prepare batches before they are due);
+        returns the offsets.  The queries go into the first n rows of `self.q`."""
+        if self.index.generation() != self.generation:
+            raise RuntimeError("the index has been appended to since this launch was captured; capture it again")
+        n = int(n)
+        if n > self.cap:
+            raise ValueError(f"batch of {n} exceeds the captured capacity {self.cap}")
+        ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (n,)))
+        if n and (ks.min() < 1 or ks.max() > self.k_max):
+            raise ValueError(f"k must lie in [1, {self.k_max}]")
+        off = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(ks, out=off[1:])
+        host = torch.zeros(self._nbytes, dtype=torch.uint8)
+        hc, ho, hk = (v.numpy() for v in self._views(host))
+        hc[0] = n
+        ho[:n + 1] = off
+        hk[:n] = ks
+        with torch.cuda.stream(self.stream):
+            self.dbuf.copy_(host.to(self.dbuf.device))
+        self.stream.synchronize()
+        return off
+
+    def replay(self, events=None):
+        """Replay the captured launch on the batch already staged (see `stage`)."""
+        if self.index.generation() != self.generation:
+            raise RuntimeError("the index has been appended to since this launch was captured; capture it again")
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            if events is not None:
+                events[0].record(self.stream)
+            self.graph.replay()
+            if events is not None:
+                events[1].record(self.stream)
+        cur.wait_stream(self.stream)
+
     def run(self, queries: Optional[torch.Tensor], k, n: Optional[int] = None,
             events=None) -> "tuple[torch.Tensor, torch.Tensor, np.ndarray]":
         """Answer `queries` (device [n, L]) with per-query k (host); returns
         (ids, lcps, offsets) views valid until the next run.  With queries
         None the first n rows of `self.q`, filled by the caller, are used.
         `events` = (start, end) are recorded around the device work."""
+        if self.index.generation() != self.generation:
+            raise RuntimeError("the index has been appended to since this launch was captured; capture it again")
         n = int(queries.shape[0]) if queries is not None else int(n)
         if n > self.cap:
             raise ValueError(f"batch of {n} exceeds the captured capacity {self.cap}")

@@ -65,6 +65,46 @@ struct TimedLaunch {
     hipEvent_t a, b;
 };
 
+// One copy of the arrays that depend on the sorted order.  An index keeps two:
+// queries read the active one, and an append merges into the other and then
+// makes it active, so a failed append leaves the index as it was.
+struct SortedCopy {
+    int64_t cap = 0;             // rows it can hold
+    uint32_t* sorted = nullptr;  // [cap][W] key form, lexicographic order
+    int32_t* perm = nullptr;     // [cap]
+    uint8_t* A = nullptr;        // [cap + kAdjPad]: fixed-size windows near the end stay inside
+    uint32_t* bmin = nullptr;    // [block_min_entries(cap)]
+    uint4* stab = nullptr;       // [search_table_entries(search_table_levels(cap))], NULL with no levels
+    uint32_t* dir = nullptr;     // [V + 2] first-token directory
+    void release() {
+        if (dir) hipFree(dir);
+        if (sorted) hipFree(sorted);
+        if (perm) hipFree(perm);
+        if (A) hipFree(A);
+        if (bmin) hipFree(bmin);
+        if (stab) hipFree(stab);
+        *this = SortedCopy();
+    }
+};
+
+// Device temporaries of small appends, kept between calls.
+struct AppendScratch {
+    int64_t cap = 0;               // new rows they can hold
+    uint32_t* sorted = nullptr;    // [cap][W] new rows in sorted order
+    int32_t* lperm = nullptr;      // [cap] local ids in sorted order
+    int64_t* ub = nullptr;         // [cap] old rows <= each sorted new row
+    uint32_t* flag = nullptr;      // device: a token >= V was seen
+    uint32_t* flag_host = nullptr;  // pinned copy of it
+    void release() {
+        if (sorted) hipFree(sorted);
+        if (lperm) hipFree(lperm);
+        if (ub) hipFree(ub);
+        if (flag) hipFree(flag);
+        if (flag_host) hipHostFree(flag_host);
+        *this = AppendScratch();
+    }
+};
+
 }  // namespace
 
 struct lcp_index {
@@ -73,14 +113,15 @@ struct lcp_index {
     int64_t N = 0;
     int32_t L = 0, V = 0;
     RowGeo g{};
-    uint32_t* d_rows = nullptr;    // id order, key form
-    uint32_t* d_sorted = nullptr;  // sorted order, key form
-    int32_t* d_perm = nullptr;
-    uint8_t* d_A = nullptr;
-    uint4* d_stab = nullptr;
+    int64_t rows_cap = 0;          // rows d_rows and d_plane can hold
+    uint32_t* d_rows = nullptr;    // [rows_cap][W] id order, key form
+    uint64_t* d_plane = nullptr;   // [plane_entries(rows_cap)] the scan's prefix plane
+    SortedCopy cp[2];
+    int cur = 0;                   // the copy queries read
     int stab_levels = 0;
-    uint32_t* d_bmin = nullptr;
-    uint2* d_plane = nullptr;
+    int search_mode = 0;           // 0: 65-ary search tables, 1: first-token directory
+    uint64_t generation = 0;       // changes of what queries read: appends, search-mode switches
+    AppendScratch app;
 
     mutable std::mutex mu;
     mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
@@ -92,14 +133,17 @@ struct lcp_index {
 
     IndexView view() const {
         IndexView v;
-        v.sorted = d_sorted;
+        const SortedCopy& c = cp[cur];
+        v.sorted = c.sorted;
         v.rows = d_rows;
-        v.perm = d_perm;
-        v.A = d_A;
-        v.stab = d_stab;
+        v.perm = c.perm;
+        v.A = c.A;
+        v.stab = c.stab;
         v.stab_levels = stab_levels;
-        v.bmin = d_bmin;
+        v.bmin = c.bmin;
         v.plane = d_plane;
+        v.dir = search_mode == 1 ? c.dir : nullptr;
+        v.dir_V = V;
         v.N = N;
         v.g = g;
         return v;
@@ -258,7 +302,7 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
                 idx->timed.push_back({0, ev[0], ev[1]});
             }
         } else {
-            const ScanPlan plan = plan_scan(idx->N, qb.Q, k_max);
+            const ScanPlan plan = plan_scan(idx->N, idx->g.W, qb.Q, k_max);
             lcp_status st = ensure_part(c, scan_partial_entries(plan, qb.Q, k_max, idx->g));
             if (st != LCP_OK) return st;
             HIP_TRY(launch_scan(ix, qb, plan, c->d_part, s, ev[0], ev[1], ev[2]));
@@ -377,12 +421,10 @@ void destroy_index(lcp_index* idx) {
     }
     for (auto e : idx->event_pool) hipEventDestroy(e);
     if (idx->d_rows) hipFree(idx->d_rows);
-    if (idx->d_sorted) hipFree(idx->d_sorted);
-    if (idx->d_perm) hipFree(idx->d_perm);
-    if (idx->d_A) hipFree(idx->d_A);
-    if (idx->d_stab) hipFree(idx->d_stab);
-    if (idx->d_bmin) hipFree(idx->d_bmin);
     if (idx->d_plane) hipFree(idx->d_plane);
+    idx->cp[0].release();
+    idx->cp[1].release();
+    idx->app.release();
     delete idx;
 }
 
@@ -431,20 +473,34 @@ lcp_status sort_rows(const void* tokens, int64_t n, const RowGeo& g, int32_t V, 
     return LCP_OK;
 }
 
-// A, search tables (sorted rows and perm in place)
-lcp_status finish_index(lcp_index* idx, hipStream_t s) {
-    const int64_t N = idx->N;
-    HIP_TRY(launch_adjacent_lcp(idx->d_sorted, N, idx->g, idx->d_A, s));
-    idx->stab_levels = search_table_levels(N);
-    if (idx->stab_levels > 0) {
-        HIP_TRY(hipMalloc(&idx->d_stab, (size_t)search_table_entries(idx->stab_levels) * sizeof(uint4)));
-        HIP_TRY(launch_search_tables(idx->d_sorted, N, idx->g.W, idx->stab_levels, idx->d_stab, s));
+// Allocate a sorted copy for `cap` rows (nothing is kept on failure).
+lcp_status alloc_copy(SortedCopy& c, int64_t cap, int W, int V, hipStream_t s) {
+    SortedCopy n;
+    n.cap = cap;
+    hipError_t e = hipMalloc(&n.sorted, (size_t)cap * W * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&n.perm, (size_t)cap * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&n.A, (size_t)cap + kAdjPad);
+    if (e == hipSuccess) e = hipMalloc(&n.bmin, (size_t)block_min_entries(cap) * sizeof(uint32_t));
+    const int levels = search_table_levels(cap);
+    if (e == hipSuccess && levels > 0) e = hipMalloc(&n.stab, (size_t)search_table_entries(levels) * sizeof(uint4));
+    if (e == hipSuccess) e = hipMalloc(&n.dir, ((size_t)V + 2) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemsetAsync(n.A, 0, (size_t)cap + kAdjPad, s);
+    if (e != hipSuccess) {
+        n.release();
+        return fail(e == hipErrorOutOfMemory ? LCP_ENOMEM : LCP_EDEVICE, "allocating the sorted arrays for %lld rows: %s",
+                    (long long)cap, hipGetErrorString(e));
     }
-    HIP_TRY(hipMalloc(&idx->d_bmin, (size_t)block_min_entries(N) * sizeof(uint32_t)));
-    HIP_TRY(launch_block_min(idx->d_perm, N, idx->d_bmin, s));
-    HIP_TRY(hipMalloc(&idx->d_plane, (size_t)N * sizeof(uint2)));
-    HIP_TRY(launch_prefix_plane(idx->d_rows, N, idx->g.W, idx->d_plane, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    c = n;
+    return LCP_OK;
+}
+
+// A, search tables and tie summaries of copy `c` holding N sorted rows
+lcp_status derive_copy(const lcp_index* idx, SortedCopy& c, int64_t N, hipStream_t s) {
+    HIP_TRY(launch_adjacent_lcp(c.sorted, N, idx->g, c.A, s));
+    const int levels = search_table_levels(N);
+    if (levels > 0) HIP_TRY(launch_search_tables(c.sorted, N, idx->g.W, levels, c.stab, s));
+    HIP_TRY(launch_block_min(c.perm, N, c.bmin, s));
+    HIP_TRY(launch_first_token_dir(c.sorted, N, idx->g, idx->V, c.dir, s));
     return LCP_OK;
 }
 
@@ -452,82 +508,152 @@ lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
     const int64_t N = idx->N;
     const int W = idx->g.W;
     HIP_TRY(hipMalloc(&idx->d_rows, (size_t)N * W * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&idx->d_sorted, (size_t)N * W * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&idx->d_perm, (size_t)N * sizeof(int32_t)));
-    // A is padded so that fixed-size windows around any position stay inside the allocation
-    HIP_TRY(hipMalloc(&idx->d_A, (size_t)N + kAdjPad));
-    HIP_TRY(hipMemsetAsync(idx->d_A + N, 0, kAdjPad, s));
-    lcp_status st = sort_rows(tokens, N, idx->g, idx->V, s, idx->d_rows, idx->d_perm);
+    HIP_TRY(hipMalloc(&idx->d_plane, (size_t)plane_entries(N) * sizeof(uint64_t)));
+    idx->rows_cap = N;
+    lcp_status st = alloc_copy(idx->cp[0], N, W, idx->V, s);
     if (st != LCP_OK) return st;
-    HIP_TRY(launch_gather_rows(idx->d_rows, idx->d_perm, N, W, idx->d_sorted, s));
-    return finish_index(idx, s);
+    SortedCopy& c = idx->cp[0];
+    st = sort_rows(tokens, N, idx->g, idx->V, s, idx->d_rows, c.perm);
+    if (st != LCP_OK) return st;
+    HIP_TRY(launch_gather_rows(idx->d_rows, c.perm, N, W, c.sorted, s));
+    st = derive_copy(idx, c, N, s);
+    if (st != LCP_OK) return st;
+    HIP_TRY(launch_prefix_plane(idx->d_rows, 0, N, W, idx->d_plane, s));
+    idx->stab_levels = search_table_levels(N);
+    HIP_TRY(hipStreamSynchronize(s));
+    return LCP_OK;
 }
 
-struct AppendTemps {
-    uint32_t* keys = nullptr;    // new rows, key form, local id order
-    uint32_t* sorted = nullptr;  // new rows, sorted
-    int32_t* perm = nullptr;     // local ids in sorted order
-    int64_t* ub = nullptr;       // old rows <= each sorted new row
-    ~AppendTemps() {
-        if (keys) hipFree(keys);
-        if (sorted) hipFree(sorted);
-        if (perm) hipFree(perm);
-        if (ub) hipFree(ub);
-    }
-};
+// Capacity after growth: room for a quarter more rows, so that a stream of
+// appends reallocates rarely.
+int64_t grown(int64_t need) {
+    const int64_t g = need + need / 4 + 1024;
+    return g < kMaxRows ? g : kMaxRows;
+}
 
-struct NewBuffers {
-    uint32_t* rows = nullptr;
-    uint32_t* sorted = nullptr;
-    int32_t* perm = nullptr;
-    uint8_t* A = nullptr;
-    ~NewBuffers() {
-        if (rows) hipFree(rows);
-        if (sorted) hipFree(sorted);
-        if (perm) hipFree(perm);
-        if (A) hipFree(A);
-    }
-};
+// Appends of at most this many rows sort them by rank in one kernel and keep
+// their temporaries between calls; larger ones take the radix sort.
+constexpr int64_t kRankSortMax = 8192;
 
 // Rows with ids N..N+n-1: the result equals a build over the concatenation.
+// The new rows are packed into the id-order rows after the old ones (and the
+// plane after the old entries), sorted, placed into the inactive sorted copy
+// together with the old rows (old first on equality: smaller ids), and the
+// adjacent LCP is copied for old rows and recomputed only where a new row was
+// inserted; the tie summaries and search tables of the merged order follow.
+// Nothing the queries read changes until every step has succeeded.
 lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_t s) {
     for (auto& kv : idx->ctx) HIP_TRY(hipStreamSynchronize(kv.first));  // no query may still read the index
     const int64_t N = idx->N;
-    const int W = idx->g.W;
-    AppendTemps t;
-    HIP_TRY(hipMalloc(&t.keys, (size_t)n * W * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&t.sorted, (size_t)n * W * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&t.perm, (size_t)n * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&t.ub, (size_t)n * sizeof(int64_t)));
-    lcp_status st = sort_rows(tokens, n, idx->g, idx->V, s, t.keys, t.perm);
-    if (st != LCP_OK) return st;  // index unchanged
-    HIP_TRY(launch_gather_rows(t.keys, t.perm, n, W, t.sorted, s));
-    HIP_TRY(launch_upper_bounds(idx->d_sorted, N, t.sorted, n, idx->g, t.ub, s));
-    NewBuffers nb;
     const int64_t M = N + n;
-    HIP_TRY(hipMalloc(&nb.rows, (size_t)M * W * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&nb.sorted, (size_t)M * W * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc(&nb.perm, (size_t)M * sizeof(int32_t)));
-    HIP_TRY(hipMalloc(&nb.A, (size_t)M + kAdjPad));
-    HIP_TRY(hipMemsetAsync(nb.A + M, 0, kAdjPad, s));
-    HIP_TRY(hipMemcpyAsync(nb.rows, idx->d_rows, (size_t)N * W * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(nb.rows + (size_t)N * W, t.keys, (size_t)n * W * sizeof(uint32_t),
-                           hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_merge_sorted(idx->d_sorted, idx->d_perm, N, t.sorted, t.perm, t.ub, n, W, nb.sorted, nb.perm, s));
+    const int W = idx->g.W;
+    const RowGeo g = idx->g;
+
+    // id-order rows and plane: in place when they have room, else new buffers
+    // that replace the old ones only on success
+    uint32_t* rows = idx->d_rows;
+    uint64_t* plane = idx->d_plane;
+    int64_t rows_cap = idx->rows_cap;
+    struct Fresh {
+        uint32_t* rows = nullptr;
+        uint64_t* plane = nullptr;
+        ~Fresh() {
+            if (rows) hipFree(rows);
+            if (plane) hipFree(plane);
+        }
+    } fresh;
+    if (rows_cap < M) {
+        rows_cap = grown(M);
+        HIP_TRY(hipMalloc(&fresh.rows, (size_t)rows_cap * W * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&fresh.plane, (size_t)plane_entries(rows_cap) * sizeof(uint64_t)));
+        HIP_TRY(hipMemcpyAsync(fresh.rows, idx->d_rows, (size_t)N * W * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(fresh.plane, idx->d_plane, (size_t)plane_entries(N) * sizeof(uint64_t),
+                               hipMemcpyDeviceToDevice, s));
+        rows = fresh.rows;
+        plane = fresh.plane;
+    }
+    SortedCopy& src = idx->cp[idx->cur];
+    SortedCopy& dst = idx->cp[idx->cur ^ 1];
+    if (dst.cap < M) {
+        dst.release();
+        lcp_status st = alloc_copy(dst, grown(M), W, idx->V, s);
+        if (st != LCP_OK) return st;
+    }
+    uint32_t* newkeys = rows + (size_t)N * W;  // the new rows, key form, id order
+
+    uint32_t* nsorted;
+    int32_t* nperm;
+    int64_t* ub;
+    struct Big {
+        uint32_t* sorted = nullptr;
+        int32_t* perm = nullptr;
+        int64_t* ub = nullptr;
+        ~Big() {
+            if (sorted) hipFree(sorted);
+            if (perm) hipFree(perm);
+            if (ub) hipFree(ub);
+        }
+    } big;
+    AppendScratch& a = idx->app;
+    if (!a.flag) {
+        HIP_TRY(hipMalloc(&a.flag, sizeof(uint32_t)));
+        HIP_TRY(hipHostMalloc(&a.flag_host, sizeof(uint32_t), hipHostMallocDefault));
+    }
+    if (n <= kRankSortMax) {
+        if (a.cap < n) {
+            if (a.sorted) hipFree(a.sorted);
+            if (a.lperm) hipFree(a.lperm);
+            if (a.ub) hipFree(a.ub);
+            a.sorted = nullptr;
+            a.lperm = nullptr;
+            a.ub = nullptr;
+            a.cap = 0;
+            HIP_TRY(hipMalloc(&a.sorted, (size_t)kRankSortMax * W * sizeof(uint32_t)));
+            HIP_TRY(hipMalloc(&a.lperm, (size_t)kRankSortMax * sizeof(int32_t)));
+            HIP_TRY(hipMalloc(&a.ub, (size_t)kRankSortMax * sizeof(int64_t)));
+            a.cap = kRankSortMax;
+        }
+        HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(uint32_t), s));
+        HIP_TRY(launch_pack_keys(tokens, n, g, (uint32_t)idx->V, newkeys, a.flag, s));
+        HIP_TRY(launch_rank_sort(newkeys, n, W, a.sorted, a.lperm, s));
+        nsorted = a.sorted;
+        nperm = a.lperm;
+        ub = a.ub;
+    } else {
+        HIP_TRY(hipMalloc(&big.sorted, (size_t)n * W * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&big.perm, (size_t)n * sizeof(int32_t)));
+        HIP_TRY(hipMalloc(&big.ub, (size_t)n * sizeof(int64_t)));
+        lcp_status st = sort_rows(tokens, n, g, idx->V, s, newkeys, big.perm);
+        if (st != LCP_OK) return st;  // index unchanged
+        HIP_TRY(launch_gather_rows(newkeys, big.perm, n, W, big.sorted, s));
+        HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(uint32_t), s));  // validated by sort_rows
+        nsorted = big.sorted;
+        nperm = big.perm;
+        ub = big.ub;
+    }
+    HIP_TRY(launch_upper_bounds(src.sorted, N, nsorted, n, g, ub, s));
+    HIP_TRY(launch_merge_sorted(src.sorted, src.perm, src.A, N, nsorted, nperm, ub, n, g, dst.sorted, dst.perm,
+                                dst.A, s));
+    const int levels = search_table_levels(M);
+    if (levels > 0) HIP_TRY(launch_search_tables(dst.sorted, M, W, levels, dst.stab, s));
+    HIP_TRY(launch_block_min(dst.perm, M, dst.bmin, s));
+    HIP_TRY(launch_first_token_dir(dst.sorted, M, g, idx->V, dst.dir, s));
+    HIP_TRY(launch_prefix_plane(rows, N, M, W, plane, s));
+    HIP_TRY(hipMemcpyAsync(a.flag_host, a.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    // swap in the merged arrays; the old ones are freed with the NewBuffers holder
-    std::swap(idx->d_rows, nb.rows);
-    std::swap(idx->d_sorted, nb.sorted);
-    std::swap(idx->d_perm, nb.perm);
-    std::swap(idx->d_A, nb.A);
-    if (idx->d_stab) hipFree(idx->d_stab);
-    idx->d_stab = nullptr;
-    if (idx->d_bmin) hipFree(idx->d_bmin);
-    idx->d_bmin = nullptr;
-    if (idx->d_plane) hipFree(idx->d_plane);
-    idx->d_plane = nullptr;
+    if (*a.flag_host) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);  // index unchanged
+
+    // commit
+    if (fresh.rows) {
+        std::swap(idx->d_rows, fresh.rows);
+        std::swap(idx->d_plane, fresh.plane);
+        idx->rows_cap = rows_cap;
+    }
+    idx->cur ^= 1;
     idx->N = M;
-    return finish_index(idx, s);
+    idx->stab_levels = levels;
+    idx->generation += 1;
+    return LCP_OK;
 }
 
 }  // namespace
@@ -605,10 +731,10 @@ lcp_status lcp_scan_topk_dev_noalloc(const lcp_index* idx, const void* queries, 
         return fail(LCP_EINVAL, "Q = %lld is above %lld, the largest batch of one allocation-free scan",
                     (long long)Q, (long long)kSliceScan);
     // everything but the partial lists, then the partial lists in what is left
-    const ScanPlan probe = plan_scan(idx->N, Q, k_max, 0);
+    const ScanPlan probe = plan_scan(idx->N, idx->g.W, Q, k_max, 0);
     const size_t fixed = scan_partial_entries(probe, Q, k_max, idx->g) * sizeof(uint64_t);
     const int64_t left = fixed < kNoAllocScratchBytes ? (int64_t)(kNoAllocScratchBytes - fixed) : 0;
-    const ScanPlan plan = plan_scan(idx->N, Q, k_max, left);
+    const ScanPlan plan = plan_scan(idx->N, idx->g.W, Q, k_max, left);
     if (plan.nparts == 0 ||
         scan_partial_entries(plan, Q, k_max, idx->g) * sizeof(uint64_t) > kNoAllocScratchBytes)
         return fail(LCP_EINVAL,
@@ -696,10 +822,28 @@ lcp_status lcp_index_info(const lcp_index* idx, int64_t* N, int32_t* L, int32_t*
 lcp_status lcp_index_views(const lcp_index* idx, const int32_t** perm, const uint8_t** adj_lcp,
                            const uint32_t** sorted_keys, const uint32_t** id_keys) {
     if (!idx) return fail(LCP_EINVAL, "index is NULL");
-    if (perm) *perm = idx->d_perm;
-    if (adj_lcp) *adj_lcp = idx->d_A;
-    if (sorted_keys) *sorted_keys = idx->d_sorted;
+    const SortedCopy& c = idx->cp[idx->cur];
+    if (perm) *perm = c.perm;
+    if (adj_lcp) *adj_lcp = c.A;
+    if (sorted_keys) *sorted_keys = c.sorted;
     if (id_keys) *id_keys = idx->d_rows;
+    return LCP_OK;
+}
+
+lcp_status lcp_index_set_search(lcp_index* idx, int32_t mode) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (mode != 0 && mode != 1) return fail(LCP_EINVAL, "search mode %d is not 0 or 1", mode);
+    std::lock_guard<std::mutex> lk(idx->mu);
+    for (auto& kv : idx->ctx) HIP_TRY(hipStreamSynchronize(kv.first));
+    if (idx->search_mode != mode) idx->generation += 1;  // captured graphs hold the old view
+    idx->search_mode = mode;
+    return LCP_OK;
+}
+
+lcp_status lcp_index_generation(const lcp_index* idx, uint64_t* generation) {
+    if (!idx || !generation) return fail(LCP_EINVAL, "NULL index or output pointer");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    *generation = idx->generation;
     return LCP_OK;
 }
 
@@ -707,7 +851,7 @@ lcp_status lcp_scan_info(const lcp_index* idx, int64_t Q, int32_t k_max, int32_t
                          int64_t* seed_rows) {
     if (!idx) return fail(LCP_EINVAL, "index is NULL");
     if (Q < 1 || k_max < 1 || k_max > LCP_K_MAX) return fail(LCP_EINVAL, "Q or k_max out of range");
-    const ScanPlan p = plan_scan(idx->N, std::min<int64_t>(Q, kSliceScan), k_max);
+    const ScanPlan p = plan_scan(idx->N, idx->g.W, std::min<int64_t>(Q, kSliceScan), k_max);
     if (query_groups) *query_groups = p.qgroups;
     if (chunks) *chunks = p.chunks;
     if (seed_rows) *seed_rows = p.seed_rows;

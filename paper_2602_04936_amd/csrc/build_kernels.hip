@@ -322,12 +322,34 @@ int64_t search_table_entries(int levels) {
 // integer arithmetic as the query's search), then store its pivot's first four
 // key words (zero past the row's end).  Entries of nodes the search never
 // reaches are zero.
-// Scan prefix plane: the first two key words of every row, id order, so the
-// full scan streams 8 bytes per row instead of the whole row.
-__global__ void k_prefix_plane(const uint32_t* __restrict__ rows, int64_t N, int W, uint2* __restrict__ plane) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    plane[i] = make_uint2(rows[i * W], W > 1 ? rows[i * W + 1] : 0u);
+// Scan prefix plane: the first two key words of every row as one 64-bit value
+// (word 0 in the high half), id order, so the full scan streams 8 bytes per
+// row instead of the whole row.  An odd N gets one zero entry after the last
+// row, so the plane is read as whole 16-byte pairs of rows.
+// Entries [from, plane_entries(to)) are written (an append fills in its new rows).
+__global__ void k_prefix_plane(const uint32_t* __restrict__ rows, int64_t from, int64_t to, int W,
+                               uint64_t* __restrict__ plane) {
+    const int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= plane_entries(to)) return;
+    plane[i] = i < to ? ((uint64_t)rows[i * W] << 32) | (W > 1 ? rows[i * W + 1] : 0u) : 0ull;
+}
+
+// First-token directory (the prefix buckets of depth one, section 6.2): one
+// thread per token value, a binary search over the sorted rows' first tokens.
+__global__ void k_first_token_dir(const uint32_t* __restrict__ sorted, int64_t N, int W, int tb, int V,
+                                  uint32_t* __restrict__ dir) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > V + 1) return;
+    int64_t lo = 0, hi = N;
+    if (t >= V) lo = N;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((int64_t)(sorted[mid * W] >> (32 - 8 * tb)) < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    dir[t] = (uint32_t)lo;
 }
 
 // Tie summaries: bmin[b] = the smallest id among sorted positions
@@ -413,34 +435,112 @@ __global__ void k_upper_bounds(const uint32_t* __restrict__ sorted, int64_t N, c
     ub[j] = lo;
 }
 
-// Old row i moves right by the number of new rows placed before it: those
-// with ub <= i (ub is non-decreasing along the sorted new rows).
-__global__ void k_merge_old(const uint32_t* __restrict__ sorted, const int32_t* __restrict__ perm, int64_t N,
-                            const int64_t* __restrict__ ub, int64_t n, int W, uint32_t* __restrict__ out_sorted,
-                            int32_t* __restrict__ out_perm) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (ub[mid] <= i)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Stable sort of n new rows by rank: row j goes to position #{i : row i <
+// row j, or row i == row j and i < j}.  Each block stages tiles of the rows in
+// LDS and every thread counts, for its own row, the rows of the tile ranked
+// before it.  O(n^2) row compares: used for small appends only.
+constexpr int kRankThreads = 256;
+__global__ __launch_bounds__(kRankThreads) void k_rank_sort(const uint32_t* __restrict__ keys, int64_t n, int W,
+                                                            int tile_rows, uint32_t* __restrict__ sorted,
+                                                            int32_t* __restrict__ lperm) {
+    extern __shared__ uint32_t tile[];
+    const int64_t j = (int64_t)blockIdx.x * kRankThreads + threadIdx.x;
+    const bool act = j < n;
+    const uint32_t* mine = keys + (act ? j : 0) * W;
+    int64_t rank = 0;
+    for (int64_t t0 = 0; t0 < n; t0 += tile_rows) {
+        const int tn = (int)(n - t0 < tile_rows ? n - t0 : tile_rows);
+        __syncthreads();
+        for (int e = threadIdx.x; e < tn * W; e += kRankThreads) tile[e] = keys[t0 * W + e];
+        __syncthreads();
+        if (act) {
+            for (int r = 0; r < tn; ++r) {
+                const uint32_t* o = tile + r * W;
+                int c = 0;
+                for (int w = 0; w < W && c == 0; ++w) {
+                    const uint32_t x = o[w], y = mine[w];
+                    c = x < y ? -1 : x > y ? 1 : 0;
+                }
+                rank += (c < 0 || (c == 0 && t0 + r < j)) ? 1 : 0;
+            }
+        }
     }
-    const int64_t dst = i + lo;
-    for (int w = 0; w < W; ++w) out_sorted[dst * W + w] = sorted[i * W + w];
-    out_perm[dst] = perm[i];
+    if (!act) return;
+    lperm[rank] = (int32_t)j;
+    for (int w = 0; w < W; ++w) sorted[rank * W + w] = mine[w];
 }
 
+// Old row i moves right by the number of new rows placed before it: those
+// with ub <= i (ub is non-decreasing along the sorted new rows).  Its id and
+// adjacent LCP go along; the LCP stays right unless a new row now precedes it,
+// which k_seam_lcp repairs.  One thread per old row finds the shift, then the
+// block copies its rows word by word.
+constexpr int kMergeThreads = 256;
+__global__ __launch_bounds__(kMergeThreads) void k_merge_old(const uint32_t* __restrict__ sorted,
+                                                             const int32_t* __restrict__ perm,
+                                                             const uint8_t* __restrict__ A, int64_t N,
+                                                             const int64_t* __restrict__ ub, int64_t n, int W,
+                                                             uint32_t* __restrict__ out_sorted,
+                                                             int32_t* __restrict__ out_perm,
+                                                             uint8_t* __restrict__ out_A) {
+    __shared__ int64_t shift[kMergeThreads];
+    const int64_t i0 = (int64_t)blockIdx.x * kMergeThreads;
+    const int64_t i = i0 + threadIdx.x;
+    int64_t lo = 0;
+    if (i < N) {
+        int64_t hi = n;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (ub[mid] <= i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        out_perm[i + lo] = perm[i];
+        out_A[i + lo] = A[i];
+    }
+    shift[threadIdx.x] = lo;
+    __syncthreads();
+    const int64_t rows = N - i0 < kMergeThreads ? N - i0 : kMergeThreads;
+    for (int64_t t = threadIdx.x; t < rows * W; t += kMergeThreads) {
+        const int64_t r = t / W;
+        const int64_t w = t - r * W;
+        out_sorted[(i0 + r + shift[r]) * W + w] = sorted[i0 * W + t];
+    }
+}
+
+// One thread per (new row, word): sorted new row j goes to ub[j] + j.
 __global__ void k_merge_new(const uint32_t* __restrict__ newrows, const int32_t* __restrict__ newperm, int64_t N,
                             const int64_t* __restrict__ ub, int64_t n, int W, uint32_t* __restrict__ out_sorted,
                             int32_t* __restrict__ out_perm) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * W) return;
+    const int64_t j = t / W;
+    const int64_t w = t - j * W;
+    const int64_t dst = ub[j] + j;
+    out_sorted[dst * W + w] = newrows[t];
+    if (w == 0) out_perm[dst] = (int32_t)(N + newperm[j]);
+}
+
+__device__ __forceinline__ int row_lcp(const uint32_t* a, const uint32_t* b, const RowGeo& g) {
+    for (int w = 0; w < g.W; ++w) {
+        const uint32_t x = a[w] ^ b[w];
+        if (x) return lcp_from_diff(w, x, g);
+    }
+    return g.L;
+}
+
+// The adjacent LCP where a new row was inserted: at its own position (against
+// the row before it) and at the next position (the row after it now follows
+// it).  Every position whose predecessor changed is one of these.
+__global__ void k_seam_lcp(const uint32_t* __restrict__ merged, int64_t M, const int64_t* __restrict__ ub, int64_t n,
+                           RowGeo g, uint8_t* __restrict__ A) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const int64_t dst = ub[j] + j;
-    for (int w = 0; w < W; ++w) out_sorted[dst * W + w] = newrows[j * W + w];
-    out_perm[dst] = (int32_t)(N + newperm[j]);
+    const int64_t P = ub[j] + j;
+    const uint32_t* row = merged + P * g.W;
+    A[P] = P == 0 ? 0 : (uint8_t)row_lcp(row - g.W, row, g);
+    if (P + 1 < M) A[P + 1] = (uint8_t)row_lcp(row, row + g.W, g);
 }
 
 // ------------------------------------------------------------ launchers
@@ -451,18 +551,42 @@ hipError_t launch_upper_bounds(const uint32_t* sorted, int64_t N, const uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, int64_t N, const uint32_t* newrows,
-                               const int32_t* newperm, const int64_t* ub, int64_t n, int W, uint32_t* out_sorted,
-                               int32_t* out_perm, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge_old, dim3(blocks_for(N, 256)), dim3(256), 0, s, sorted, perm, N, ub, n, W, out_sorted,
-                       out_perm);
-    hipLaunchKernelGGL(k_merge_new, dim3(blocks_for(n, 256)), dim3(256), 0, s, newrows, newperm, N, ub, n, W,
+hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, const uint8_t* A, int64_t N,
+                               const uint32_t* newrows, const int32_t* newperm, const int64_t* ub, int64_t n, RowGeo g,
+                               uint32_t* out_sorted, int32_t* out_perm, uint8_t* out_A, hipStream_t s) {
+    const int W = g.W;
+    hipLaunchKernelGGL(k_merge_old, dim3(blocks_for(N, kMergeThreads)), dim3(kMergeThreads), 0, s, sorted, perm, A, N,
+                       ub, n, W, out_sorted, out_perm, out_A);
+    hipLaunchKernelGGL(k_merge_new, dim3(blocks_for(n * W, 256)), dim3(256), 0, s, newrows, newperm, N, ub, n, W,
                        out_sorted, out_perm);
+    hipLaunchKernelGGL(k_seam_lcp, dim3(blocks_for(n, 256)), dim3(256), 0, s, out_sorted, N + n, ub, n, g, out_A);
     return hipGetLastError();
 }
 
-hipError_t launch_prefix_plane(const uint32_t* rows, int64_t N, int W, uint2* plane, hipStream_t s) {
-    hipLaunchKernelGGL(k_prefix_plane, dim3(blocks_for(N, 256)), dim3(256), 0, s, rows, N, W, plane);
+hipError_t launch_first_token_dir(const uint32_t* sorted, int64_t N, RowGeo g, int V, uint32_t* dir, hipStream_t s) {
+    hipLaunchKernelGGL(k_first_token_dir, dim3(blocks_for((int64_t)V + 2, 256)), dim3(256), 0, s, sorted, N, g.W, g.tb,
+                       V, dir);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_sort(const uint32_t* keys, int64_t n, int W, uint32_t* sorted, int32_t* lperm, hipStream_t s) {
+    int tile = 8192 / W;  // 32 KB of LDS
+    if (tile > kRankThreads) tile = kRankThreads;
+    hipLaunchKernelGGL(k_rank_sort, dim3(blocks_for(n, kRankThreads)), dim3(kRankThreads),
+                       (size_t)tile * W * sizeof(uint32_t), s, keys, n, W, tile, sorted, lperm);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_keys(const void* tokens, int64_t n, RowGeo g, uint32_t V, uint32_t* keys, uint32_t* bad,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_keys, dim3(blocks_for(n * g.W, 256)), dim3(256), 0, s, tokens, n, g, V, keys, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_plane(const uint32_t* rows, int64_t from, int64_t to, int W, uint64_t* plane, hipStream_t s) {
+    const int64_t n = plane_entries(to) - from;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prefix_plane, dim3(blocks_for(n, 256)), dim3(256), 0, s, rows, from, to, W, plane);
     return hipGetLastError();
 }
 

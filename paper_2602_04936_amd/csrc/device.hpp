@@ -44,6 +44,10 @@ __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l) {
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
+// a value every lane holds alike, as a scalar
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
 
 // value of lane (lane - 1); lane 0 receives its own value
 __device__ __forceinline__ uint32_t from_lower_lane(uint32_t v) {

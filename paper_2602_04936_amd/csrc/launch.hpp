@@ -26,15 +26,30 @@ hipError_t launch_adjacent_lcp(const uint32_t* sorted, int64_t N, RowGeo g, uint
 // ub[j] = number of rows of `sorted` (N rows) that are <= row j of `newrows` (n rows, sorted)
 hipError_t launch_upper_bounds(const uint32_t* sorted, int64_t N, const uint32_t* newrows, int64_t n, RowGeo g,
                                int64_t* ub, hipStream_t s);
-// merge two sorted row sets (old first on ties); new ids are N + newperm[j]
-hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, int64_t N, const uint32_t* newrows,
-                               const int32_t* newperm, const int64_t* ub, int64_t n, int W, uint32_t* out_sorted,
-                               int32_t* out_perm, hipStream_t s);
+// merge two sorted row sets (old first on ties); new ids are N + newperm[j];
+// the adjacent LCP of old rows is carried over and recomputed where new rows
+// were inserted
+hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, const uint8_t* A, int64_t N,
+                               const uint32_t* newrows, const int32_t* newperm, const int64_t* ub, int64_t n, RowGeo g,
+                               uint32_t* out_sorted, int32_t* out_perm, uint8_t* out_A, hipStream_t s);
+// key-form rows of n token rows (flag set on a token >= V), and their stable
+// order by rank (small n)
+hipError_t launch_pack_keys(const void* tokens, int64_t n, RowGeo g, uint32_t V, uint32_t* keys, uint32_t* bad,
+                            hipStream_t s);
+hipError_t launch_rank_sort(const uint32_t* keys, int64_t n, int W, uint32_t* sorted, int32_t* lperm, hipStream_t s);
 hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
                                 hipStream_t s);
 
-// scan prefix plane: key words 0 and 1 of each row, id order
-hipError_t launch_prefix_plane(const uint32_t* rows, int64_t N, int W, uint2* plane, hipStream_t s);
+// scan prefix plane: key words 0 (high half) and 1 of each row as one 64-bit
+// value, id order, padded with a zero entry to an even length
+__host__ __device__ inline int64_t plane_entries(int64_t N) { return (N + 1) & ~(int64_t)1; }
+// entries [from, plane_entries(to)) of the plane of rows [0, to)
+hipError_t launch_prefix_plane(const uint32_t* rows, int64_t from, int64_t to, int W, uint64_t* plane, hipStream_t s);
+
+// first-token directory: dir[t] = the first sorted position whose first token
+// is >= t, for t < V, and dir[V] = dir[V + 1] = N (the prefix buckets of
+// depth one)
+hipError_t launch_first_token_dir(const uint32_t* sorted, int64_t N, RowGeo g, int V, uint32_t* dir, hipStream_t s);
 
 // tie summaries: smallest id of each run of 64 sorted positions
 inline int64_t block_min_entries(int64_t N) { return (N + kWave - 1) / kWave; }
@@ -63,7 +78,9 @@ struct IndexView {
     const uint8_t* A;        // [N] adjacent LCP
     const uint4* stab;       // search tables (may be null when levels == 0)
     const uint32_t* bmin;    // [ceil(N/64)] smallest id of each run of 64 sorted positions
-    const uint2* plane;      // [N] key words 0 and 1 of each row, id order (the scan's stream)
+    const uint64_t* plane;   // [plane_entries(N)] (word 0 << 32) | word 1 of each row, id order (the scan's stream)
+    const uint32_t* dir;     // null, or [dir_V + 2]: the first sorted position whose first token is >= t
+    int dir_V;               // first-token values the directory covers (V)
     int stab_levels;
     int64_t N;
     RowGeo g;
@@ -111,12 +128,12 @@ hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& 
 
 // Full scan.  `part` must hold scan_partial_entries(...) keys.
 struct ScanPlan {
-    int tq;             // queries per wave
+    int tq;             // queries per wave (a query group)
     int nr;             // list registers (capacity 64*nr >= k_max)
-    int chunks;         // row chunks over [seed_rows, N)
-    int qgroups;        // query groups (grid y), 4*tq queries each
-    int nparts;         // partial lists per query: seed_chunks + chunks (grid x)
-    int seed_chunks;    // one-step chunks over the sampled rows (first in grid x)
+    int chunks;         // row chunks (one wave each) over [seed_rows, N)
+    int qgroups;        // query groups; each streams every row once
+    int nparts;         // waves, and partial lists per query: seed_chunks + chunks
+    int seed_chunks;    // chunks over the sampled rows (the first waves of a group)
     int64_t seed_rows;  // rows [0, seed_rows) whose LCP histogram sets each query's starting limit
     int seed_parts;     // histogram blocks per query
     int64_t seed_chunk_rows;
@@ -126,7 +143,7 @@ struct ScanPlan {
 // nparts == 0 in the result means not even one seed chunk and one row chunk
 // per query fit in it.
 constexpr int64_t kScanPartBudget = (int64_t)256 << 20;
-ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max, int64_t part_budget_bytes = kScanPartBudget);
+ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budget_bytes = kScanPartBudget);
 
 // Per-call scratch of the scan, carved from one device allocation.
 struct ScanScratch {

@@ -357,6 +357,18 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     const uint64_t qb2 = ((uint64_t)(g.W > 2 ? q[2] : 0u) << 32) | (g.W > 3 ? q[3] : 0u);
     int lo = 0, hi = N;
     int lcp_lo = -1, lcp_hi = -1;  // LCP(q, T[lo-1]), LCP(q, T[hi])
+    // with the first-token directory the search starts in the query's bucket:
+    // the rows around it have other first tokens, so their LCP with q is 0
+    int levels = ix.stab_levels;
+    if (ix.dir != nullptr) {
+        const uint32_t t0 = q[0] >> (32 - 8 * g.tb);
+        const uint32_t t = t0 < (uint32_t)ix.dir_V ? t0 : (uint32_t)ix.dir_V;
+        lo = (int)ix.dir[t];
+        hi = (int)ix.dir[t + 1];
+        lcp_lo = 0;
+        lcp_hi = 0;
+        levels = 0;
+    }
     int p;
     int lL, lR;
     int wbase;
@@ -391,7 +403,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
         const int b65 = n - (kWave + 1) * a65;
         int lc;
         bool less;
-        if (depth < ix.stab_levels) {
+        if (depth < levels) {
             // pivot's first four key words from the table (one coalesced load)
             const uint4 e = depth == 0 ? root : ix.stab[level_start + node * kWave + lane];
             const uint64_t ka = ((uint64_t)e.x << 32) | e.y;
@@ -432,7 +444,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
             hi = lo0 + (cnt + 1) * a65 + (int)((uint32_t)((cnt + 1) * b65) / (kWave + 1));
             lcp_hi = readlane_i(lc, cnt);
         }
-        if (depth < ix.stab_levels) {
+        if (depth < levels) {
             node = node * (kWave + 1) + cnt;
             level_start = level_start * (kWave + 1) + kWave;
             ++depth;

@@ -2,27 +2,26 @@
 // then per-query top-k), the baseline the paper's range scan is measured
 // against (section 7, Table "TAL range-scan vs full-scan").
 //
-// Grid = (row chunks) x (query groups).  A block's 4 waves stream the same
-// row chunk (one row per lane, 4 tiles of 64 rows in flight, ascending ids)
-// and each wave serves its own TQ queries, keeping one lane-distributed top-k
-// list per query.  Once a list holds k entries, every row still to come has a
-// larger id than all of them, so it can only enter with an LCP at least one
-// more than the k-th entry's LCP t: the hot loop tests the first t + 1 tokens
-// of the row's first key word with one AND and one compare against a
-// pre-masked query word, and computes the exact LCP only for rows that pass.
-// Before the scan, an LCP histogram of every query against the first rows
-// gives each query a starting limit, so most rows fail the filter from the
-// first tile on.  Each wave appends the entries of its per-chunk lists that can
-// still be in the answer to the query's compact partial list; a second kernel
-// merges them.
+// The pass streams the 8-byte prefix plane (key words 0 and 1 of every row,
+// id order).  Queries are split into groups of TQ; each wave streams one row
+// chunk for the TQ queries of its group (16 bytes, two rows, per lane and
+// load, the next step's loads in flight while the current step is tested),
+// keeping one top-k list per query.  Once a list holds k entries, every row
+// still to come has a larger id than all of them, so it can only enter with an
+// LCP at least one more than the k-th entry's LCP t: the hot loop tests the
+// first t + 1 tokens of the row's first two key words with one 64-bit compare
+// (and two ANDs when t + 1 tokens are fewer than 64 bits) against a pre-masked
+// query value, and computes the exact LCP only for rows that pass.  Before the
+// scan, an LCP histogram of every query against the first rows gives each
+// query a starting limit, so most rows fail the filter from the first step
+// on.  Each wave appends the entries of its lists that can still be in the
+// answer to the query's compact partial list; a second kernel merges them.
 #include "device.hpp"
 #include "launch.hpp"
 
 namespace lcpx {
 
 constexpr int kScanWaves = 4;
-constexpr int kScanUnroll = 4;
-constexpr int64_t kSeedChunkRows = kScanUnroll * kWave;  // one step of a block
 // Each query's fill count sits on its own 128-byte line: every wave of every
 // chunk adds to the counts of its queries, and counts sharing a line would
 // serialise those atomics in one L2 channel.
@@ -81,9 +80,9 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const 
         const bool act = r < r1;
         int lc = g.L;
         if (act) {
-            const uint2 pw = ix.plane[r];
-            const uint32_t x0 = pw.x ^ qw[0];
-            const uint32_t x1 = g.W > 1 ? pw.y ^ qw[1] : 0u;
+            const uint64_t pw = ix.plane[r];
+            const uint32_t x0 = (uint32_t)(pw >> 32) ^ qw[0];
+            const uint32_t x1 = g.W > 1 ? (uint32_t)pw ^ qw[1] : 0u;
             if (x0) {
                 lc = lcp_from_diff(0, x0, g);
             } else if (x1) {
@@ -145,23 +144,10 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_seed_limit(QueryBatch qb
     if (lane == 0) gthr[qi] = lim;
 }
 
-// gthr[q] holds the smallest k-th key any chunk has reached for query q: a row
+// gthr[q] holds the smallest k-th key any wave has reached for query q: a row
 // whose key is not below it cannot be in q's answer (that k-th key is the
-// k-th best of k real rows), so every chunk may skip such rows.  The limit
+// k-th best of k real rows), so every wave may skip such rows.  The limit
 // only prunes; the merged answer is the unique exact top-k either way.
-//
-// Code layout: the unrolled hot loop only tests (tile, query) pairs and sets
-// a bit for each pair with a candidate lane; a single, non-unrolled slow path
-// then serves the flagged pairs, with each query's list and filter in LDS, so
-// the kernel stays small enough for the instruction cache.
-template <int NR>
-struct ScanQueryState {  // per (wave, query), in LDS
-    uint64_t list[NR * kWave];
-    uint64_t lim;
-    uint64_t msk, qm;
-    int32_t kk;  // min(k, N)
-    int32_t pad_;
-};
 
 // One launch before the scan: zero the fill counts and histograms (a kernel,
 // not a memset, so the sequence can be captured in a graph) and compute the
@@ -176,184 +162,252 @@ __global__ void k_scan_prep(QueryBatch qb, RowGeo g, uint32_t* __restrict__ zero
     }
 }
 
-// Blocks x < seed_chunks scan the sampled rows [0, seed_rows) in chunks of
-// seed_chunk_rows, normally one step (there the starting limit lets rows at
-// its LCP through, so that work is spread thin); the others scan
-// [seed_rows, N) in chunks of chunk_rows.
+// Per (wave, query) filter state in LDS.
+struct ScanFilter {
+    uint64_t msk, qm;  // a row passes when (plane & msk) == qm
+    uint64_t lim;      // the wave's limit key for the query
+    int32_t kk;        // min(k, N)
+    int32_t pad_;
+};
+
+// Geometry of one scan launch (grid x = qgroups * ceil(nparts / kScanWaves)).
+struct ScanGrid {
+    int64_t seed_rows;        // rows [0, seed_rows) are the seed sample
+    int64_t seed_chunk_rows;  // rows per seed wave
+    int64_t chunk_rows;       // rows per main wave, over [seed_rows, N)
+    int nparts;               // waves (partial lists) per query group: seed waves first
+    int seed_chunks;
+    int qgroups;
+    int lstride;              // list entries kept per (wave, query): k_max
+};
+
+// One wave streams one row chunk of the prefix plane for the TQ queries of its
+// block's query group; the block's 4 waves take 4 consecutive chunks.  Each
+// lane reads 16 bytes (two rows) per load, kScanU loads per step (512 rows),
+// and the next step's loads are in flight while the current step is tested.
+// Consecutive blocks (after the XCD remap below) take the same rows for
+// different query groups, so a chunk is fetched into one XCD's L2 once.
+//
+// Code layout: the unrolled hot loop only tests, per query, whether any of the
+// step's rows passes its filter (one 64-bit compare per row, and two ANDs
+// when the filter keeps part of the 64 bits), and sets one bit per flagged
+// query; a single non-unrolled slow path then serves the flagged queries with
+// the query's list and filter in LDS.
+//
 // At the end each wave appends, per query, the entries of its list that do
 // not exceed the query's limit to the query's partial list (cap entries at
 // part + q * cap, fill count in cnt[q]); the append order does not matter,
 // the merge ranks by key.
+constexpr int kScanU = 4;                                  // 16-byte loads per lane per step
+constexpr int64_t kPairRows = 2 * kWave;                   // rows of one 16-byte load of the wave
+constexpr int64_t kScanStepRows = kScanU * kPairRows;      // rows per wave step
+constexpr int kGthrEvery = 4;                              // steps between pick-ups of shared limits
+
 template <int NR, int TQ>
-__global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, QueryBatch qb, const uint32_t* qkeys,
-                                                             int64_t seed_rows, int seed_chunks,
-                                                             int64_t seed_chunk_rows, int64_t chunk_rows,
+__global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, QueryBatch qb,
+                                                             const uint32_t* __restrict__ qkeys, ScanGrid sg,
                                                              int64_t cap, uint64_t* __restrict__ part,
                                                              uint32_t* __restrict__ cnt,
                                                              uint64_t* __restrict__ gthr) {
-    static_assert(kScanUnroll * TQ <= 64, "one flag bit per (tile, query)");
-    // bit u * TQ of each tile u: shifted by i, the bits of query i's tiles
-    constexpr uint64_t kTileBits = [] {
-        uint64_t b = 0;
-        for (int u = 0; u < kScanUnroll; ++u) b |= 1ull << (u * TQ);
-        return b;
-    }();
+    static_assert(TQ <= 64, "one flag bit per query");
     extern __shared__ uint64_t s_dyn64[];
-    ScanQueryState<NR>* st_all = reinterpret_cast<ScanQueryState<NR>*>(s_dyn64);  // [kScanWaves*TQ]
-    uint32_t* s_q = reinterpret_cast<uint32_t*>(st_all + kScanWaves * TQ);       // [kScanWaves*TQ][W]
     const RowGeo g = ix.g;
-    const int lane = lane_id();
-    const int64_t qblock = (int64_t)blockIdx.y * kScanWaves * TQ;
-    for (int idx = threadIdx.x; idx < kScanWaves * TQ * g.W; idx += kScanWaves * kWave)
-        s_q[idx] = qblock * g.W + idx < qb.Q * g.W ? qkeys[qblock * g.W + idx] : 0u;
-    for (int idx = threadIdx.x; idx < kScanWaves * TQ; idx += kScanWaves * kWave) {
-        // query slots past the end of the batch get a filter nothing matches
-        const bool real = qblock + idx < qb.Q;
-        st_all[idx].lim = kKeyMax;
-        st_all[idx].msk = 0;
-        st_all[idx].qm = real ? 0 : 1;
-        const int ki = real ? query_k(qb, qblock + idx) : 1;
-        st_all[idx].kk = (int)((int64_t)ki < ix.N ? (int64_t)ki : ix.N);
-    }
-    for (int idx = threadIdx.x; idx < kScanWaves * TQ * NR * kWave; idx += kScanWaves * kWave)
-        st_all[idx / (NR * kWave)].list[idx % (NR * kWave)] = kKeyMax;
-    __syncthreads();
-    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int64_t q0i = qblock + (int64_t)wv * TQ;
-    if (q0i >= qb.Q) return;
-    const int ntq = (int)(qb.Q - q0i < TQ ? qb.Q - q0i : TQ);
-    const int64_t N = ix.N;
     const int W = g.W;
-    ScanQueryState<NR>* st = st_all + wv * TQ;
-    const uint32_t* qwords = s_q + wv * TQ * W;
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // blocks are dealt to the 8 XCDs round robin; renumber them so that each
+    // XCD holds a contiguous run of logical blocks
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned xcd = b & 7u, q8 = nb >> 3, r8 = nb & 7u;
+    const unsigned lb = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + (b >> 3);
+    const int grp = (int)(lb % (unsigned)sg.qgroups);
+    const int pidx = (int)(lb / (unsigned)sg.qgroups) * kScanWaves + wv;
+    const int64_t q0i = (int64_t)grp * TQ;
+    const int ntq = (int)(qb.Q - q0i < TQ ? qb.Q - q0i : TQ);
 
+    uint32_t* s_q = reinterpret_cast<uint32_t*>(s_dyn64);  // [TQ][W] query words, shared by the block
+    const int qwords64 = (TQ * W + 1) / 2;
+    ScanFilter* filt = reinterpret_cast<ScanFilter*>(s_dyn64 + qwords64) + wv * TQ;
+    uint64_t* lists = s_dyn64 + qwords64 + (size_t)kScanWaves * TQ * (sizeof(ScanFilter) / 8) +
+                      (size_t)wv * TQ * sg.lstride;
+    for (int t = threadIdx.x; t < TQ * W; t += kScanWaves * kWave)
+        s_q[t] = t < ntq * W ? qkeys[q0i * W + t] : 0u;
+    __syncthreads();
+    if (pidx >= sg.nparts) return;
+
+    const int64_t N = ix.N;
     int64_t r_lo, r_hi;
-    if ((int)blockIdx.x < seed_chunks) {
-        r_lo = (int64_t)blockIdx.x * seed_chunk_rows;
-        r_hi = r_lo + seed_chunk_rows < seed_rows ? r_lo + seed_chunk_rows : seed_rows;
+    if (pidx < sg.seed_chunks) {
+        r_lo = (int64_t)pidx * sg.seed_chunk_rows;
+        r_hi = r_lo + sg.seed_chunk_rows < sg.seed_rows ? r_lo + sg.seed_chunk_rows : sg.seed_rows;
     } else {
-        r_lo = seed_rows + (int64_t)((int)blockIdx.x - seed_chunks) * chunk_rows;
-        r_hi = r_lo + chunk_rows < N ? r_lo + chunk_rows : N;
+        r_lo = sg.seed_rows + (int64_t)(pidx - sg.seed_chunks) * sg.chunk_rows;
+        r_hi = r_lo + sg.chunk_rows < N ? r_lo + sg.chunk_rows : N;
     }
-    // rows of the next step are requested before the current step is
-    // tested, so a step's loads overlap the previous step's compute; one
-    // 8-byte load per row from the prefix plane (its second word is 0 for
-    // one-word rows).  Positions past the chunk re-read its last row.
-    uint2 nx[kScanUnroll];
+    // pairs of rows [p_lo, p_hi): r_lo is even, and an odd N has a zero entry
+    // after its last row; loads past the chunk re-read its last pair.  The
+    // first step's loads go out before the filters are set up.
+    const uint4* __restrict__ pl = reinterpret_cast<const uint4*>(ix.plane);
+    const int64_t p_lo = r_lo >> 1, p_last = ((r_hi + 1) >> 1) - 1;
+    uint4 nx[kScanU];
 #pragma unroll
-    for (int u = 0; u < kScanUnroll; ++u) {
-        const int64_t id = r_lo + u * kWave + lane;
-        nx[u] = ix.plane[id < r_hi ? id : r_hi - 1];
+    for (int u = 0; u < kScanU; ++u) {
+        const int64_t pp = p_lo + u * kWave + lane;
+        nx[u] = pl[pp < p_last ? pp : p_last];
     }
+    // filters from the starting limits; query slots past the batch get one
+    // that nothing matches
+    if (lane < TQ) {
+        ScanFilter f;
+        const bool real = lane < ntq;
+        f.lim = real ? gthr[q0i + lane] : kKeyMax;
+        const int ki = real ? query_k(qb, q0i + lane) : 1;
+        f.kk = (int)((int64_t)ki < N ? (int64_t)ki : N);
+        f.pad_ = 0;
+        const uint32_t* q = s_q + lane * W;
+        const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
+        limit_filter(f.lim, r_lo, q01, g, f.msk, f.qm);
+        if (!real) {
+            f.msk = 0;
+            f.qm = 1;
+        }
+        filt[lane] = f;
+    }
+    for (int e = lane; e < TQ * sg.lstride; e += kWave) lists[e] = kKeyMax;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // the filters as wave-uniform values (scalar registers), reloaded from
+    // LDS only after the slow path or a pick-up of shared limits changed one
+    uint64_t fm[TQ], fq[TQ];
+    auto load_filters = [&]() {
+#pragma unroll
+        for (int i = 0; i < TQ; ++i) {
+            fm[i] = uniform64(filt[i].msk);
+            fq[i] = uniform64(filt[i].qm);
+        }
+    };
+    load_filters();
     int it = 0;
-    for (int64_t base = r_lo; base < r_hi; base += kScanUnroll * kWave, ++it) {
-        if ((it & 7) == 0) {
-            // pick up tighter limits reached by other chunks: lane i reads query
+    for (int64_t base = r_lo; base < r_hi; base += kScanStepRows, ++it) {
+        if (it > 0 && it % kGthrEvery == 0) {
+            // pick up tighter limits reached by other waves: lane i reads query
             // i's limit with a plain load (a stale value only prunes less)
             const uint64_t mine = lane < ntq ? gthr[q0i + lane] : kKeyMax;
 #pragma unroll 1
             for (int i = 0; i < ntq; ++i) {
                 const uint64_t gv = readlane64(mine, i);
-                if (gv < st[i].lim) {
-                    const uint32_t* q = qwords + i * W;
-                    const uint64_t q01 = ((uint64_t)q[0] << 32) | (W >= 2 ? q[1] : 0u);
+                if (gv < filt[i].lim) {
+                    const uint32_t* q = s_q + i * W;
+                    const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
                     uint64_t msk, qm;
                     limit_filter(gv, base, q01, g, msk, qm);
                     if (lane == 0) {
-                        st[i].lim = gv;
-                        st[i].msk = msk;
-                        st[i].qm = qm;
+                        filt[i].lim = gv;
+                        filt[i].msk = msk;
+                        filt[i].qm = qm;
                     }
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            load_filters();
         }
-        // first two key words of each lane's row (word 0 in the high half)
-        uint64_t w01[kScanUnroll];
+        // the step's rows, as 64-bit plane values (word 0 high): row
+        // base + u * 128 + 2 * lane + h is v[2u + h]
+        uint64_t v[2 * kScanU];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) w01[u] = ((uint64_t)nx[u].x << 32) | nx[u].y;
-        if (base + kScanUnroll * kWave < r_hi) {
+        for (int u = 0; u < kScanU; ++u) {
+            v[2 * u] = ((uint64_t)nx[u].y << 32) | nx[u].x;
+            v[2 * u + 1] = ((uint64_t)nx[u].w << 32) | nx[u].z;
+        }
+        if (base + kScanStepRows < r_hi) {
+            const int64_t pn = p_lo + (int64_t)(it + 1) * (kScanU * kWave);
 #pragma unroll
-            for (int u = 0; u < kScanUnroll; ++u) {
-                const int64_t id = base + (kScanUnroll + u) * kWave + lane;
-                nx[u] = ix.plane[id < r_hi ? id : r_hi - 1];
+            for (int u = 0; u < kScanU; ++u) {
+                const int64_t pp = pn + u * kWave + lane;
+                nx[u] = pl[pp < p_last ? pp : p_last];
             }
         }
-        // filters stay in VGPRs (wave-uniform values): one AND pair and one
-        // 64-bit compare per (tile, query)
-        uint64_t msk[TQ], qm[TQ];
-#pragma unroll
-        for (int i = 0; i < TQ; ++i) {
-            msk[i] = st[i].msk;
-            qm[i] = st[i].qm;
-        }
-        // hot loop: which queries have a candidate lane in any of the step's
-        // tiles (the tiles' ballots are OR-ed, one scalar op per pair); a
-        // flagged query gets a bit for each of its tiles, and the slow path
-        // skips tiles without a candidate.  Lanes past the chunk re-read its
-        // last row, so they may flag a query; the slow path drops them.
-        // A filter that needs both words whole (the usual case once a limit
-        // asks for 64 bits or more) is a plain equality test.
+        // hot loop: which queries have a row passing their filter this step.
+        // Lanes past the chunk re-read its last pair, so they may flag a
+        // query; the slow path drops them.
         uint64_t flagged = 0;
 #pragma unroll
         for (int i = 0; i < TQ; ++i) {
+            const uint64_t msk = fm[i], qm = fq[i];
             uint64_t any = 0;
-            if (msk[i] == ~0ull) {
+            if (msk == ~0ull) {
 #pragma unroll
-                for (int u = 0; u < kScanUnroll; ++u) any |= ballot(w01[u] == qm[i]);
+                for (int t = 0; t < 2 * kScanU; ++t) any |= ballot(v[t] == qm);
             } else {
 #pragma unroll
-                for (int u = 0; u < kScanUnroll; ++u) any |= ballot((w01[u] & msk[i]) == qm[i]);
+                for (int t = 0; t < 2 * kScanU; ++t) any |= ballot((v[t] & msk) == qm);
             }
-            if (any) flagged |= kTileBits << i;
+            flagged |= any ? (1ull << i) : 0ull;
         }
-        // slow path, one flagged pair at a time (tiles in ascending order)
+        // slow path, one flagged query at a time, its rows in id order
+        const bool any_flagged = flagged != 0;
+#pragma unroll 1
         while (flagged) {
-            const int bit = low_lane(flagged);
+            const int i = low_lane(flagged);
             flagged &= flagged - 1;
-            const int u = bit / TQ;
-            const int i = bit - u * TQ;
-            const int64_t id = base + u * kWave + lane;
-            const bool act = id < r_hi;
-            uint64_t w = w01[0];
-#pragma unroll
-            for (int uu = 1; uu < kScanUnroll; ++uu) w = u == uu ? w01[uu] : w;
-            const uint32_t* q = qwords + i * W;
+            const uint32_t* q = s_q + i * W;
             const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
-            const bool cand = act && (w & st[i].msk) == st[i].qm;
-            if (ballot(cand) == 0) continue;  // another tile of this query had the candidate
-            int lc = -1;
-            if (cand) {
-                const uint64_t x = w ^ q01;
-                if (x >> 32)
-                    lc = lcp_from_diff(0, (uint32_t)(x >> 32), g);
-                else if ((uint32_t)x)
-                    lc = lcp_from_diff(1, (uint32_t)x, g);
-                else
-                    lc = W > 2 ? lcp_tail(ix.rows + id * W, q, g, 2) : g.L;
-            }
-            const int kk = st[i].kk;
-            const uint64_t lim = st[i].lim;
-            const uint64_t key = rank_key(lc, (uint32_t)id);
+            ScanFilter f = filt[i];
+            uint64_t* lp = lists + (size_t)i * sg.lstride;
             WaveList<NR> lst;
 #pragma unroll
-            for (int r = 0; r < NR; ++r) lst.v[r] = st[i].list[r * kWave + lane];
-            lst.offer(key, cand && key < lim, kk);
-            const uint64_t kth = lst.get(kk - 1);
-            uint64_t nlim = lim;
-            if (kth < lim) {
-                nlim = kth;
-                if (lane == 0) atomicMin((unsigned long long*)(gthr + q0i + i), (unsigned long long)kth);
+            for (int r = 0; r < NR; ++r) {
+                const int e = r * kWave + lane;
+                lst.v[r] = e < sg.lstride ? lp[e] : kKeyMax;
             }
-            uint64_t nm, nq;
-            limit_filter(nlim, base + (u + 1) * kWave, q01, g, nm, nq);
+            bool touched = false;
+#pragma unroll 1
+            for (int t = 0; t < 2 * kScanU; ++t) {
+                uint64_t w = v[0];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) st[i].list[r * kWave + lane] = lst.v[r];
-            if (lane == 0) {
-                st[i].lim = nlim;
-                st[i].msk = nm;
-                st[i].qm = nq;
+                for (int tt = 1; tt < 2 * kScanU; ++tt) w = t == tt ? v[tt] : w;
+                const int u = t >> 1, h = t & 1;
+                const int64_t id = base + u * kPairRows + 2 * lane + h;
+                const bool cand = id < r_hi && (w & f.msk) == f.qm;
+                if (ballot(cand) == 0) continue;
+                touched = true;
+                int lc = -1;
+                if (cand) {
+                    const uint64_t x = w ^ q01;
+                    if (x >> 32)
+                        lc = lcp_from_diff(0, (uint32_t)(x >> 32), g);
+                    else if ((uint32_t)x)
+                        lc = lcp_from_diff(1, (uint32_t)x, g);
+                    else
+                        lc = W > 2 ? lcp_tail(ix.rows + id * W, q, g, 2) : g.L;
+                }
+                const uint64_t key = rank_key(lc, (uint32_t)id);
+                lst.offer(key, cand && key < f.lim, f.kk);
+                const uint64_t kth = lst.get(f.kk - 1);
+                if (kth < f.lim) {
+                    f.lim = kth;
+                    if (lane == 0) atomicMin((unsigned long long*)(gthr + q0i + i), (unsigned long long)kth);
+                }
+                // rows still to come: the second row of this pair, or the next pairs
+                limit_filter(f.lim, base + u * kPairRows + (h == 0 ? 1 : kPairRows), q01, g, f.msk, f.qm);
+            }
+            if (touched) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int e = r * kWave + lane;
+                    if (e < sg.lstride) lp[e] = lst.v[r];
+                }
+                if (lane == 0) filt[i] = f;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
+        if (any_flagged) load_filters();
     }
 
     // entries above a valid limit cannot be in the answer; each list is
@@ -364,14 +418,15 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     int mine = 0;
 #pragma unroll 1
     for (int i = 0; i < ntq; ++i) {
-        const int kk = st[i].kk;
-        const uint64_t keep = st[i].lim;
+        const int kk = filt[i].kk;
+        const uint64_t keep = filt[i].lim;
+        const uint64_t* lp = lists + (size_t)i * sg.lstride;
         int n = 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int e = r * kWave + lane;
-            const uint64_t v = st[i].list[e];
-            n += popc64(ballot(e < kk && v != kKeyMax && v <= keep));
+            const uint64_t x = e < kk ? lp[e] : kKeyMax;
+            n += popc64(ballot(x != kKeyMax && x <= keep));
         }
         mine = lane == i ? n : mine;
     }
@@ -382,7 +437,8 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         const int n = readlane_i(mine, i);
         if (n == 0) continue;
         uint64_t* dst = part + (q0i + i) * cap + (uint32_t)readlane_i((int)at, i);
-        for (int e = lane; e < n; e += kWave) dst[e] = st[i].list[e];
+        const uint64_t* lp = lists + (size_t)i * sg.lstride;
+        for (int e = lane; e < n; e += kWave) dst[e] = lp[e];
     }
 }
 
@@ -497,30 +553,55 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan_merge(QueryBatch qb
 
 static int nr_for(int32_t k_max) { return k_max <= 64 ? 1 : k_max <= 128 ? 2 : k_max <= 256 ? 4 : 16; }
 
-static int tq_for(int nr, int64_t Q) {
-    // queries per wave, from the compiled set, no more than the batch needs
-    int tq;
-    switch (nr) {
-        case 1: tq = 8; break;
-        case 2: tq = 8; break;
-        case 4: tq = 4; break;
-        default: tq = 1; break;
+// Bytes of LDS a scan block needs: the query words, then per wave TQ filters
+// and TQ lists of k_max entries.
+static size_t scan_block_lds(int tq, int32_t k_max, int W) {
+    return ((size_t)tq * W * sizeof(uint32_t) + 7) / 8 * 8 +
+           (size_t)kScanWaves * tq * (sizeof(ScanFilter) + (size_t)k_max * sizeof(uint64_t));
+}
+constexpr size_t kScanLdsBudget = 40 << 10;  // per block: at least 4 blocks (16 waves) per CU
+
+// Queries per wave, from the compiled set for the list size: the fewest
+// (query slot, row) tests for the batch, then the most queries per wave,
+// within the LDS budget (one query per wave always fits).
+static int tq_for(int nr, int32_t k_max, int64_t Q, int W) {
+    static const int c1[] = {16, 8, 2, 1}, c2[] = {8, 1}, c4[] = {4, 1}, c16[] = {1};
+    const int* c = nr == 1 ? c1 : nr == 2 ? c2 : nr == 4 ? c4 : c16;
+    const int n = nr == 1 ? 4 : nr == 16 ? 1 : 2;
+    int best = 1;
+    int64_t best_slots = Q;
+    for (int i = n - 1; i >= 0; --i) {  // ascending tq: a larger one wins ties
+        const int tq = c[i];
+        if (tq > 1 && scan_block_lds(tq, k_max, W) > kScanLdsBudget) continue;
+        const int64_t slots = (Q + tq - 1) / tq * tq;
+        if (slots <= best_slots) {
+            best = tq;
+            best_slots = slots;
+        }
     }
-    while (tq > 1 && (int64_t)kScanWaves * tq / 2 >= Q) tq = tq > 4 ? 4 : 1;
-    return tq;
+    return best;
 }
 
 // Rows sampled for the starting limits, and the main pass's chunking.
-constexpr int64_t kChunkMinRows = 2048;
+constexpr int64_t kChunkMinRows = 2 * kScanStepRows;
 constexpr int64_t kSeedRows = 65536;
+constexpr int64_t kScanTargetWaves = 8192;  // 32 per CU
 
-ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max, int64_t part_budget_bytes) {
+ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budget_bytes) {
     ScanPlan p;
     p.nr = nr_for(k_max);
-    p.tq = tq_for(p.nr, Q);
-    const int64_t per_group = (int64_t)kScanWaves * p.tq;
-    p.qgroups = (int)((Q + per_group - 1) / per_group);
-    p.seed_rows = N < kSeedRows ? N : kSeedRows;
+    p.tq = tq_for(p.nr, k_max, Q, W);
+    p.qgroups = (int)((Q + p.tq - 1) / p.tq);
+    // the sample: 65,536 rows, and for batches of at most 1,024 queries up to
+    // 1/32 of a larger database (at most 262,144 rows), so that the starting
+    // limits stay as tight on large databases (the sample's cost grows with
+    // Q times its size)
+    int64_t S = kSeedRows;
+    if (Q <= 1024) {
+        const int64_t big = (N / 32 + kScanStepRows - 1) / kScanStepRows * kScanStepRows;
+        S = big > S ? (big < 4 * kSeedRows ? big : 4 * kSeedRows) : S;
+    }
+    p.seed_rows = N < S ? N : S;
     // seed blocks per query: enough blocks in all to fill the device, but at
     // most 32, since every block adds its counts to the query's histogram
     // with global atomics on the same few addresses
@@ -536,32 +617,30 @@ ScanPlan plan_scan(int64_t N, int64_t Q, int32_t k_max, int64_t part_budget_byte
         p.seed_chunk_rows = p.chunk_rows = 0;
         return p;
     }
-    // sampled rows: one-step chunks while the grid stays near 4096 blocks,
+    // sampled rows: one-step waves while the grid stays near the target,
     // fewer and longer ones for many query groups or a tight partial budget
-    int64_t sc = (p.seed_rows + kSeedChunkRows - 1) / kSeedChunkRows;
-    const int64_t by_grid = 4096 / p.qgroups;
+    int64_t sc = (p.seed_rows + kScanStepRows - 1) / kScanStepRows;
+    const int64_t by_grid = kScanTargetWaves / 2 / p.qgroups;
     if (sc > by_grid) sc = by_grid;
     if (sc > max_by_mem / 2) sc = max_by_mem / 2;
     if (sc < 1) sc = 1;
     p.seed_chunk_rows = (p.seed_rows + sc - 1) / sc;
-    p.seed_chunk_rows = (p.seed_chunk_rows + kSeedChunkRows - 1) / kSeedChunkRows * kSeedChunkRows;
+    p.seed_chunk_rows = (p.seed_chunk_rows + kScanStepRows - 1) / kScanStepRows * kScanStepRows;
     p.seed_chunks = (int)((p.seed_rows + p.seed_chunk_rows - 1) / p.seed_chunk_rows);
-    // main: rows [seed_rows, N); aim for >= 4096 blocks (16 per CU), chunks of
-    // >= kChunkMinRows rows, partials <= 256 MiB
+    // main: rows [seed_rows, N); aim for the target wave count, chunks of at
+    // least kChunkMinRows rows (whole steps), partials within the budget
     const int64_t rest = N - p.seed_rows;
     if (rest <= 0) {
         p.chunk_rows = kChunkMinRows;
         p.chunks = 0;
     } else {
-        int64_t chunks = (4096 + p.qgroups - 1) / p.qgroups;
+        int64_t chunks = (kScanTargetWaves + p.qgroups - 1) / p.qgroups;
         const int64_t max_by_rows = (rest + kChunkMinRows - 1) / kChunkMinRows;
         if (chunks > max_by_rows) chunks = max_by_rows;
         if (chunks > max_by_mem - p.seed_chunks) chunks = max_by_mem - p.seed_chunks;
-        if (chunks > 65535 - p.seed_chunks) chunks = 65535 - p.seed_chunks;
         if (chunks < 1) chunks = 1;
-        const int64_t step = (int64_t)kScanUnroll * kWave;
         int64_t rows = (rest + chunks - 1) / chunks;
-        rows = (rows + step - 1) / step * step;
+        rows = (rows + kScanStepRows - 1) / kScanStepRows * kScanStepRows;
         p.chunk_rows = rows;
         p.chunks = (int)((rest + rows - 1) / rows);
     }
@@ -588,12 +667,19 @@ size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, const R
 
 template <int NR, int TQ>
 static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, const ScanScratch& sc,
-                          hipStream_t s) {
-    const size_t shm =
-        (size_t)kScanWaves * TQ * (sizeof(ScanQueryState<NR>) + (size_t)ix.g.W * sizeof(uint32_t));
-    hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)p.nparts, (unsigned)p.qgroups), dim3(kScanWaves * kWave), shm,
-                       s, ix, qb, sc.qkeys, p.seed_rows, p.seed_chunks, p.seed_chunk_rows, p.chunk_rows, sc.cap,
-                       sc.part, sc.cnt, sc.gthr);
+                          int32_t k_max, hipStream_t s) {
+    ScanGrid sg;
+    sg.seed_rows = p.seed_rows;
+    sg.seed_chunk_rows = p.seed_chunk_rows;
+    sg.chunk_rows = p.chunk_rows;
+    sg.nparts = p.nparts;
+    sg.seed_chunks = p.seed_chunks;
+    sg.qgroups = p.qgroups;
+    sg.lstride = k_max;
+    const size_t shm = scan_block_lds(TQ, k_max, ix.g.W);
+    const int64_t blocks = (int64_t)p.qgroups * ((p.nparts + kScanWaves - 1) / kScanWaves);
+    hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)blocks), dim3(kScanWaves * kWave), shm, s, ix, qb, sc.qkeys,
+                       sg, sc.cap, sc.part, sc.cnt, sc.gthr);
 }
 
 hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* scratch, hipStream_t s,
@@ -610,15 +696,15 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
                        0, s, qb, ix.N, ix.g.L, p.seed_rows, sc.hist, sc.gthr);
     if (ev0) hipEventRecord(ev0, s);
     switch (p.nr * 100 + p.tq) {
-        case 108: launch_scan_t<1, 8>(ix, qb, p, sc, s); break;
-        case 104: launch_scan_t<1, 4>(ix, qb, p, sc, s); break;
-        case 101: launch_scan_t<1, 1>(ix, qb, p, sc, s); break;
-        case 208: launch_scan_t<2, 8>(ix, qb, p, sc, s); break;
-        case 204: launch_scan_t<2, 4>(ix, qb, p, sc, s); break;
-        case 201: launch_scan_t<2, 1>(ix, qb, p, sc, s); break;
-        case 404: launch_scan_t<4, 4>(ix, qb, p, sc, s); break;
-        case 401: launch_scan_t<4, 1>(ix, qb, p, sc, s); break;
-        case 1601: launch_scan_t<16, 1>(ix, qb, p, sc, s); break;
+        case 116: launch_scan_t<1, 16>(ix, qb, p, sc, qb.k_max, s); break;
+        case 108: launch_scan_t<1, 8>(ix, qb, p, sc, qb.k_max, s); break;
+        case 102: launch_scan_t<1, 2>(ix, qb, p, sc, qb.k_max, s); break;
+        case 101: launch_scan_t<1, 1>(ix, qb, p, sc, qb.k_max, s); break;
+        case 208: launch_scan_t<2, 8>(ix, qb, p, sc, qb.k_max, s); break;
+        case 201: launch_scan_t<2, 1>(ix, qb, p, sc, qb.k_max, s); break;
+        case 404: launch_scan_t<4, 4>(ix, qb, p, sc, qb.k_max, s); break;
+        case 401: launch_scan_t<4, 1>(ix, qb, p, sc, qb.k_max, s); break;
+        case 1601: launch_scan_t<16, 1>(ix, qb, p, sc, qb.k_max, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

@@ -489,3 +489,139 @@ def test_autotuned_shapes_agree(P):
                 idx.topk_persistent(qd, cnt, kd, od, 100, ids, lcps, blocks=shape.blocks)
             torch.cuda.synchronize()
             assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps), shape
+
+
+def test_append_large_batch_and_after_a_rejected_one(P):
+    """An append of more than 8,192 rows (radix-sorted on its own), then a
+    rejected append (token >= V), then a small one: the index equals a build
+    over the accepted rows at every point."""
+    import torch
+    rng = np.random.default_rng(77)
+    L, V = 12, 16
+    a = synth.random_rows(rng, 20000, L, V)
+    b = np.concatenate([synth.random_rows(rng, 12000, L, V), a[:300]])
+    c = synth.random_rows(rng, 50, L, V)
+    qs = np.concatenate([synth.random_rows(rng, 30, L, V), a[:10], b[-10:], c[:5]])
+    ks = rng.integers(1, 120, qs.shape[0]).astype(np.int32)
+    with P.Index(a, V) as idx:
+        g0 = idx.generation()
+        idx.append(b)
+        assert idx.generation() == g0 + 1
+        bad = c.copy()
+        bad[7, 3] = V
+        with pytest.raises(P.LcpError) as e:
+            idx.append(bad)
+        assert e.value.status == -4 and idx.N == len(a) + len(b) and idx.generation() == g0 + 1
+        for rows in ((a, b), (a, b, c)):
+            whole = np.concatenate(rows)
+            if len(rows) == 3:
+                idx.append(c)
+            va = {k: v.cpu().numpy() for k, v in idx.views().items()}
+            r = idx.topk(qs, ks)
+            torch.cuda.synchronize()
+            with P.Index(whole, V) as ref:
+                vb = {k: v.cpu().numpy() for k, v in ref.views().items()}
+            for key in ("perm", "adj_lcp", "sorted_keys", "id_keys"):
+                assert (va[key] == vb[key]).all(), (len(rows), key)
+            wi, wl, _ = oracle.c_topk(whole, qs, ks)
+            assert (r.ids.cpu().numpy() == wi).all() and (r.lcps.cpu().numpy() == wl).all()
+
+
+def test_captured_launch_refuses_replay_after_append(P):
+    """A graph captured before an append holds the old arrays: replaying it is
+    refused on the host (nothing stale is launched); a new capture works."""
+    import torch
+    from paper_2602_04936_amd import batching
+    w = synth.c3_like(50_000, 200, seed=15)
+    qd = P.to_device_tokens(w.queries)
+    with P.Index(w.db, w.V) as idx:
+        cl = batching.CapturedLaunch(idx, cap_queries=200, k_max=100)
+        cl.run(qd, w.k)
+        torch.cuda.synchronize()
+        idx.append(w.queries[:20])
+        with pytest.raises(RuntimeError):
+            cl.run(qd, w.k)
+        cl2 = batching.CapturedLaunch(idx, cap_queries=200, k_max=100)
+        gi, gl, _ = cl2.run(qd, w.k)
+        ref = idx.topk(qd, w.k)
+        torch.cuda.synchronize()
+        assert torch.equal(gi, ref.ids) and torch.equal(gl, ref.lcps)
+        wi, wl, _ = oracle.c_topk(np.concatenate([w.db, w.queries[:20]]), w.queries, w.k)
+        assert (gi.cpu().numpy() == wi).all() and (gl.cpu().numpy() == wl).all()
+
+
+@pytest.mark.parametrize("name", ["c1", "long_ties", "c3_like"])
+def test_work_stats_match_the_oracle(P, name):
+    """lcp_topk_stats: the cutoff c, the rows above it and the rows tied at it,
+    per query, equal what the oracle's LCPs give; the answers equal lcp_topk."""
+    import torch
+    if name == "c1":
+        w = synth.c1_tiny()
+        sel = np.arange(w.Q)
+    elif name == "long_ties":
+        w = synth.long_ties()
+        sel = np.arange(0, w.Q, 4)
+    else:
+        w = synth.c3_like(100_000, 300, seed=16)
+        sel = np.arange(w.Q)
+    qs, ks = w.queries[sel], w.k[sel]
+    with P.Index(w.db, w.V) as idx:
+        r, st = idx.topk_stats(qs, ks)
+        ref = idx.topk(qs, ks)
+        torch.cuda.synchronize()
+        assert torch.equal(r.ids, ref.ids) and torch.equal(r.lcps, ref.lcps)
+        st = st.cpu().numpy()
+    for j in range(len(sel)):
+        c, n_gt, tied = _tie_shape(w.db, qs[j], ks[j])
+        assert tuple(st[j, :3]) == (c, n_gt, tied), (name, j)
+        m = min(int(ks[j]), w.N) - n_gt
+        assert (st[j, 3] == 0) == (m == 0) and (st[j, 3] == 1) == (m > 0 and c == 0)
+
+
+@pytest.mark.parametrize("case", ["c1", "c2_like", "c3_like", "random_v2", "random_v300", "random_v65536",
+                                  "tokens_beyond_v", "sparse_first_tokens"])
+def test_first_token_directory_search(P, case):
+    """Both insertion-point searches (65-ary tables, first-token directory)
+    give the oracle's answers, also for query first tokens no row has and
+    tokens >= V; switching the search bumps the generation."""
+    import torch
+    rng = np.random.default_rng(sum(map(ord, case)))
+    if case == "c1":
+        w = synth.c1_tiny()
+        db, qs, ks, V = w.db, w.queries, w.k, w.V
+    elif case == "c2_like":
+        db = synth.prototype_rows(rng, synth.random_rows(rng, 512, 64, 256), 60000, 0.05, 256)
+        qs = np.concatenate([synth.prototype_rows(rng, db[:512], 200, 0.05, 256), db[:50]])
+        ks, V = rng.integers(1, 100, qs.shape[0]).astype(np.int32), 256
+    elif case == "c3_like":
+        w = synth.c3_like(150_000, 400, seed=19)
+        db, qs, ks, V = w.db, w.queries, w.k, w.V
+    elif case.startswith("random_v"):
+        V = int(case[len("random_v"):])
+        L = 9
+        db = synth.random_rows(rng, 30000, L, V)
+        qs = np.concatenate([synth.random_rows(rng, 100, L, V), db[rng.integers(0, 30000, 40)]])
+        ks = rng.integers(1, 300, qs.shape[0]).astype(np.int32)
+    elif case == "tokens_beyond_v":
+        V = 300
+        db = synth.random_rows(rng, 20000, 6, V)
+        qs = synth.random_rows(rng, 64, 6, 65536)  # first tokens mostly >= V
+        qs[:8, 0] = 299
+        qs[8:16, 0] = 0
+        ks = rng.integers(1, 40, 64).astype(np.int32)
+    else:  # first tokens drawn from 5 of 4,096 values: most queries fall in empty buckets
+        V = 4096
+        db = synth.random_rows(rng, 20000, 5, V)
+        db[:, 0] = rng.choice(np.array([3, 700, 701, 2048, 4095], np.uint16), 20000)
+        qs = synth.random_rows(rng, 80, 5, V)
+        qs[:40, 0] = db[rng.integers(0, 20000, 40), 0]
+        ks = rng.integers(1, 70, 80).astype(np.int32)
+    wi, wl, _ = oracle.c_topk(db, qs, ks)
+    with P.Index(db, V) as idx:
+        g0 = idx.generation()
+        for mode in (0, 1, 0):
+            idx.set_search(mode)
+            r = idx.topk(qs, ks)
+            torch.cuda.synchronize()
+            assert (r.ids.cpu().numpy() == wi).all() and (r.lcps.cpu().numpy() == wl).all(), (case, mode)
+        assert idx.generation() == g0 + 2
