@@ -54,6 +54,9 @@ def parse():
                     help="sustained run per energy reading (0 disables the energy section)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain 1-byte elementwise copy of this size (profiler counter calibration)")
+    ap.add_argument("--calib-gather-mib", type=int, default=0,
+                    help="also gather this many MiB of random 64-byte rows from a 1 GiB table "
+                         "(profiler counter calibration for scattered reads)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -216,21 +219,52 @@ def main():
     bw_gbs = bw_bytes / (bw_ms / bw_n * 1e-3) / 1e9
 
     # ---- the same Q=32 pass with the 256 MB Infinity Cache flushed before each
-    # rep (a 512 MiB write between reps), so the plane comes from HBM
-    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
-    cold = []
-    for _ in range(10):
-        flush.fill_(1)
-        torch.cuda.synchronize()
-        idx.set_kernel_timing(True)
-        idx.kernel_time(1)
-        idx.scan_topk(qbw, kbw, out=(bw_ids, bw_lcp))
-        c_ms, c_n = idx.kernel_time(1)
-        idx.set_kernel_timing(False)
-        cold.append(c_ms / max(c_n, 1))
-    del flush
-    cold_us = float(np.median(cold)) * 1e3
+    # rep, so the plane comes from HBM: a 512 MiB read (clean lines), and a
+    # 512 MiB write (the dirty lines are written back while the pass runs)
+    flush = torch.ones(512 << 20, dtype=torch.uint8, device=dev)
+
+    def cold_pass(ix, q, kk, out, write_flush):
+        times = []
+        for _ in range(10):
+            if write_flush:
+                flush.fill_(1)
+            else:
+                flush.sum()
+            torch.cuda.synchronize()
+            ix.set_kernel_timing(True)
+            ix.kernel_time(1)
+            ix.scan_topk(q, kk, out=out)
+            c_ms, c_n = ix.kernel_time(1)
+            ix.set_kernel_timing(False)
+            times.append(c_ms / max(c_n, 1))
+        return float(np.median(times)) * 1e3
+
+    cold_us = cold_pass(idx, qbw, kbw, (bw_ids, bw_lcp), False)
+    cold_w_us = cold_pass(idx, qbw, kbw, (bw_ids, bw_lcp), True)
     cold_gbs = bw_bytes / (cold_us * 1e-6) / 1e9
+
+    def stream_reference(nbytes):
+        """torch.sum over nbytes of int64, hot and after the read flush: what a
+        plain streaming reduction reaches on the same data size."""
+        x = torch.ones(nbytes // 8, dtype=torch.int64, device=dev)
+        res = {}
+        for name, pre in (("hot", None), ("cold", lambda: flush.sum())):
+            ts = []
+            for _ in range(10):
+                if pre:
+                    pre()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                torch.sum(x)
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b) * 1e3)
+            us = float(np.median(ts))
+            res[name + "_us"] = round(us, 2)
+            res[name + "_GBps"] = round(nbytes / (us * 1e-6) / 1e9, 1)
+        del x
+        return res
 
     # ---- a database larger than the Infinity Cache: c3's generator at N=8M
     large = None
@@ -259,6 +293,8 @@ def main():
         lm, ln = lidx.kernel_time(1)
         lidx.set_kernel_timing(False)
         l_pass_us = lm / max(ln, 1) * 1e3
+        l_cold_us = cold_pass(lidx, lq[:32], args.k, lbw, False)
+        l_passes = lidx.scan_info(32, args.k)[0]
         t = time.perf_counter()
         for _ in range(2):
             lidx.scan_topk(lq, args.k, out=lo[0])
@@ -268,7 +304,13 @@ def main():
                  "index_qps": round(l_qps, 1), "index_ms_per_step": round(wl.Q / l_qps * 1e3, 5),
                  "scan_qps": round(l_scan_qps, 1),
                  "scan_pass_q32_us": round(l_pass_us, 2),
-                 "scan_pass_q32_plane_GBps": round(wl.N * plane_bytes / (l_pass_us * 1e-6) / 1e9, 1)}
+                 "scan_pass_q32_plane_GBps": round(wl.N * plane_bytes * l_passes / (l_pass_us * 1e-6) / 1e9, 1),
+                 "scan_pass_q32_cold_us": round(l_cold_us, 2),
+                 "scan_pass_q32_cold_plane_GBps": round(wl.N * plane_bytes * l_passes / (l_cold_us * 1e-6) / 1e9, 1),
+                 "scan_pass_q32_cold_frac": round(wl.N * plane_bytes * l_passes / (l_cold_us * 1e-6) / 1e9 /
+                                                  HBM_PEAK_GBS, 4),
+                 "passes_over_db_q32": l_passes,
+                 "streaming_reference_torch_sum": stream_reference(wl.N * plane_bytes)}
         lidx.close()
         del wl, lq, lo
         log(args, f"[bench] larger than the Infinity Cache: {large}")
@@ -460,7 +502,7 @@ def main():
 
             energy["index"] = meter.measure(run_index, es, sync_every=64)
             energy["full_scan"] = meter.measure(run_scan(idx), es, sync_every=1)
-            energy["prefix_bucket_scan"] = prefix_bucket_sweep(P, w, args.k, dev, meter, es)
+            energy["prefix_bucket_scan"] = prefix_bucket_sweep(P, w, args.k, dev, meter, es, idle=iw)
             ji, js = energy["index"].get("j_per_query"), energy["full_scan"].get("j_per_query")
             energy["index_vs_full_scan_energy_ratio"] = round(js / ji, 1) if ji and js else None
             meter.close()
@@ -474,6 +516,8 @@ def main():
         st = synth.SensorStream(seed=1005)
         hist = np.concatenate(list(st.steps(1000)), axis=0)
         sidx = P.Index(hist, synth.SensorStream.V)
+        # room for every append of both runs below, so that no append allocates
+        sidx.reserve(sidx.N + 2 * (args.sensor_steps // 1000 + 1) * st.S)
 
         def append(index, batch):
             index.append(batch)
@@ -482,8 +526,15 @@ def main():
         rep = serve.run_step_stream(sidx, st.steps(args.sensor_steps), rate_hz=4000.0, k=5, append_every=1000,
                                     append=append)
         rep["final_rows"] = rep.pop("index").N
+        rep["append_mode"] = "lcp_index_append (sorted merge into the second sorted copy, room reserved beforehand)"
+        rep["append_ms_median"] = round(float(np.median(rep["append_ms"])), 3) if rep["append_ms"] else None
+        # the same loop unpaced: every step is released when the previous one is done
+        un = serve.run_step_stream(sidx, st.steps(args.sensor_steps), rate_hz=None, k=5, append_every=1000,
+                                   append=append)
+        un.pop("index")
+        rep["unpaced"] = {key: un[key] for key in ("steps", "achieved_hz", "p50_step_ms", "p99_step_ms",
+                                                   "max_step_ms", "appends", "append_ms")}
         sidx.close()
-        rep["append_mode"] = "lcp_index_append (sorted merge)"
         sensor = rep
         log(args, f"[bench] sensor stream: {sensor}")
 
@@ -500,6 +551,18 @@ def main():
         for _ in range(3):
             torch.bitwise_not(a, out=b)
         torch.cuda.synchronize()
+        del a, b
+    if args.calib_gather_mib > 0:
+        # rows of 64 bytes (16 int32) from a 1 GiB table at random positions:
+        # reads n * (64 + 8) bytes (rows and int64 positions), writes n * 64
+        table = torch.ones((1 << 30) // 64, 16, dtype=torch.int32, device=dev)
+        n = (args.calib_gather_mib << 20) // 64
+        pos = torch.randint(0, table.shape[0], (n,), device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+        out_g = torch.empty((n, 16), dtype=torch.int32, device=dev)
+        for _ in range(3):
+            torch.index_select(table, 0, pos, out=out_g)
+        torch.cuda.synchronize()
+        del table, pos, out_g
 
     out = {
         "metric": "queries/s at N=2M,L=32,k=10 (index vs full scan); p50/p99 ms at fixed QPS",
@@ -549,7 +612,9 @@ def main():
                           "frac": round(bw_gbs / HBM_PEAK_GBS, 4),
                           "avg_kernel_us": round(bw_ms / bw_n * 1e3, 2),
                           "avg_call_us": round(bw_call_us, 2),
-                          "cold_kernel_us": round(cold_us, 2), "cold_achieved": round(cold_gbs, 1)},
+                          "cold_kernel_us": round(cold_us, 2), "cold_achieved": round(cold_gbs, 1),
+                          "cold_after_write_flush_us": round(cold_w_us, 2),
+                          "streaming_reference_torch_sum": stream_reference(w.N * plane_bytes)},
         "large_db": large,
         "build_ms": round(build_ms, 2),
         "serving": serving,
@@ -619,13 +684,15 @@ def work_shape(st, N, k, row_bytes, probes):
     }
 
 
-def prefix_bucket_sweep(P, w, k, dev, meter, seconds):
+def prefix_bucket_sweep(P, w, k, dev, meter, seconds, idle=None):
     """Full scans confined to prefix buckets (the bucketed range scan of the
     paper's energy theorem): at depth d the rows are split by their first d
     tokens (c3's hierarchy gives 16^d buckets), one index per bucket, and each
     query scans only the bucket of its own first d tokens.  J/query and the
     mean rows scanned per query, for d = 0, 1, 2 (B = 1, 16, 256).  A query
-    whose prefix no row has scans nothing."""
+    whose prefix no row has scans nothing.  Besides J/query (board power over
+    the query rate), the share above the idle draw is given: at small buckets
+    the calls are short and the idle draw dominates."""
     import torch
     out = {}
     for d in (0, 1, 2):
@@ -660,9 +727,14 @@ def prefix_bucket_sweep(P, w, k, dev, meter, seconds):
             return nq
 
         rep = meter.measure(run, seconds, sync_every=1)
+        above = None
+        if idle is not None and rep.get("watts") and rep.get("queries_per_s"):
+            above = (rep["watts"] - idle) / rep["queries_per_s"]
         out[str(len(groups) if d else 1)] = {"depth": d, "buckets_with_queries": len(groups), "queries": int(nq),
                                               "mean_rows_scanned": round(float(scanned), 1),
-                                              "j_per_query": rep.get("j_per_query"), "watts": rep.get("watts")}
+                                              "j_per_query": rep.get("j_per_query"),
+                                              "j_per_query_above_idle": above, "watts": rep.get("watts"),
+                                              "queries_per_s": rep.get("queries_per_s")}
         for sub, _, _, _ in subs:
             sub.close()
         torch.cuda.synchronize()

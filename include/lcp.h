@@ -210,6 +210,19 @@ lcp_status lcp_scan_topk_dev_noalloc(const lcp_index* index, const void* queries
 lcp_status lcp_index_append(lcp_index* index, const void* tokens, int64_t n, void* stream);
 
 /*
+ * Room for `rows` rows in total (N included) for later appends: the id-order
+ * rows, both copies of the sorted arrays and the append temporaries are grown
+ * now, so that appends of at most 8,192 rows each, up to that total, allocate
+ * nothing (for callers that append from a paced loop).  The arrays queries
+ * read may move: the generation advances (see lcp_index_generation).
+ *   rows   : 0 <= rows <= 2^31 - 2^16; rows <= N only prepares the second copy.
+ *   stream : runs the copies; synchronised before the call returns, as is
+ *            every stream the index has been used on.
+ * Errors: LCP_EINVAL, LCP_ENOMEM, LCP_EDEVICE (the index stays usable).
+ */
+lcp_status lcp_index_reserve(lcp_index* index, int64_t rows, void* stream);
+
+/*
  * Graph-capturable form of lcp_topk_dev for batches of uneven size and k:
  * the batch size is read on the device, so a HIP graph captured once replays
  * for any batch up to the capacity of the buffers it was captured with.  The
@@ -240,8 +253,8 @@ lcp_status lcp_topk_persistent(const lcp_index* index, const void* queries, int6
 
 /*
  * Number of changes to what queries read since the build (0 after it): each
- * successful lcp_index_append and each lcp_index_set_search that switches the
- * mode adds one.  A HIP graph captured while it had one value must not be
+ * successful lcp_index_append and lcp_index_reserve, and each
+ * lcp_index_set_search that switches the mode, adds one.  A HIP graph captured while it had one value must not be
  * replayed once it has another.  Errors: LCP_EINVAL for a NULL argument.
  */
 lcp_status lcp_index_generation(const lcp_index* index, uint64_t* generation);
@@ -249,7 +262,7 @@ lcp_status lcp_index_generation(const lcp_index* index, uint64_t* generation);
 /*
  * How the index path finds a query's insertion point (both give the same
  * answers; this only changes the work):
- *   mode 0 (default): a static 65-ary search whose top three levels come from
+ *   mode 0: a static 65-ary search whose top three levels come from
  *          the search tables (each step compares the query with 64 pivots'
  *          first 16 bytes in one coalesced load).
  *   mode 1: the first-token directory, a table of V + 2 sorted positions
@@ -257,10 +270,15 @@ lcp_status lcp_index_generation(const lcp_index* index, uint64_t* generation);
  *          prefix bucket of depth one, section 6.2, Definitions "Prefix
  *          Bucket" and "Thermal-Aware Logic"); the 65-ary search then runs
  *          over that range on the rows themselves.
+ * The build picks the one with fewer dependent steps for rows like the
+ * database's (the directory costs one lookup and then the steps over the
+ * query's first-token bucket; ties keep the tables); this call overrides it.
  * The call synchronises every stream the index has been used on.
  * Errors: LCP_EINVAL (NULL index, mode not 0 or 1), LCP_EDEVICE.
  */
 lcp_status lcp_index_set_search(lcp_index* index, int32_t mode);
+/* The search in use (0 or 1).  Errors: LCP_EINVAL for a NULL argument. */
+lcp_status lcp_index_search_mode(const lcp_index* index, int32_t* mode);
 
 /* Synchronise every stream the index has been used on, then free it.  NULL is a no-op. */
 void lcp_index_free(lcp_index* index);

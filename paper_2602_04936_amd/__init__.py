@@ -55,6 +55,8 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_topk_persistent": [vp, vp, i64, vp, vp, vp, i32, vp, vp, i32, vp],
         "lcp_index_generation": [vp, ctypes.POINTER(ctypes.c_uint64)],
         "lcp_index_set_search": [vp, i32],
+        "lcp_index_reserve": [vp, i64, vp],
+        "lcp_index_search_mode": [vp, ctypes.POINTER(i32)],
         "lcp_set_kernel_timing": [vp, i32],
         "lcp_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -249,6 +251,16 @@ class Index:
         """Insertion-point search of the index path (lcp_index_set_search): 0 = 65-ary search tables,
         1 = first-token directory.  Answers are the same either way."""
         _check(lib.lcp_index_set_search(self._h, int(mode)))
+
+    def search_mode(self) -> int:
+        """The insertion-point search in use (lcp_index_search_mode): 0 tables, 1 directory."""
+        m = ctypes.c_int32()
+        _check(lib.lcp_index_search_mode(self._h, ctypes.byref(m)))
+        return m.value
+
+    def reserve(self, rows: int, stream=None):
+        """Room for `rows` rows in total, so that later appends allocate nothing (lcp_index_reserve)."""
+        _check(lib.lcp_index_reserve(self._h, int(rows), _stream_handle(stream)))
 
     def generation(self) -> int:
         """Changes of what queries read (lcp_index_generation); graphs captured at another value are stale."""

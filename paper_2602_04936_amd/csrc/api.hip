@@ -93,8 +93,9 @@ struct AppendScratch {
     uint32_t* sorted = nullptr;    // [cap][W] new rows in sorted order
     int32_t* lperm = nullptr;      // [cap] local ids in sorted order
     int64_t* ub = nullptr;         // [cap] old rows <= each sorted new row
-    uint32_t* flag = nullptr;      // device: a token >= V was seen
+    uint32_t* flag = nullptr;      // device: the last append (by epoch) that saw a token >= V
     uint32_t* flag_host = nullptr;  // pinned copy of it
+    uint32_t epoch = 0;            // appends so far that used the flag
     void release() {
         if (sorted) hipFree(sorted);
         if (lperm) hipFree(lperm);
@@ -473,6 +474,35 @@ lcp_status sort_rows(const void* tokens, int64_t n, const RowGeo& g, int32_t V, 
     return LCP_OK;
 }
 
+// Dependent search steps of the 65-ary search over n rows (down to at most 64
+// rows, then the last step).
+int search_steps(double n) {
+    int s = 1;
+    while (n > kWave) {
+        n /= kWave + 1;
+        ++s;
+    }
+    return s;
+}
+
+// Whether the first-token directory beats the search tables as the top of the
+// search, by dependent steps: the directory costs one lookup and then the
+// steps over the query's bucket (size weighted by rows, as queries drawn like
+// the rows see it); the tables cost their levels and the steps below them.
+// A tie keeps the tables, whose steps read one coalesced line instead of 64
+// rows.
+bool directory_pays(const std::vector<uint32_t>& dir, int64_t N, int levels) {
+    double sq = 0;
+    for (size_t t = 0; t + 1 < dir.size(); ++t) {
+        const double b = (double)dir[t + 1] - (double)dir[t];
+        sq += b * b;
+    }
+    const double bucket = sq / (double)N;
+    double below = (double)N;
+    for (int d = 0; d < levels; ++d) below /= kWave + 1;
+    return 1 + search_steps(bucket) < levels + search_steps(below);
+}
+
 // Allocate a sorted copy for `cap` rows (nothing is kept on failure).
 lcp_status alloc_copy(SortedCopy& c, int64_t cap, int W, int V, hipStream_t s) {
     SortedCopy n;
@@ -520,7 +550,10 @@ lcp_status build_into(lcp_index* idx, const void* tokens, hipStream_t s) {
     if (st != LCP_OK) return st;
     HIP_TRY(launch_prefix_plane(idx->d_rows, 0, N, W, idx->d_plane, s));
     idx->stab_levels = search_table_levels(N);
+    std::vector<uint32_t> dir((size_t)idx->V + 2);
+    HIP_TRY(hipMemcpyAsync(dir.data(), c.dir, dir.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    idx->search_mode = directory_pays(dir, N, idx->stab_levels) ? 1 : 0;
     return LCP_OK;
 }
 
@@ -534,6 +567,84 @@ int64_t grown(int64_t need) {
 // Appends of at most this many rows sort them by rank in one kernel and keep
 // their temporaries between calls; larger ones take the radix sort.
 constexpr int64_t kRankSortMax = 8192;
+
+// Make `c` hold `cap` rows, keeping its first N rows' arrays.
+lcp_status grow_copy(lcp_index* idx, SortedCopy& c, int64_t cap, int64_t N, hipStream_t s) {
+    if (c.cap >= cap) return LCP_OK;
+    SortedCopy n;
+    lcp_status st = alloc_copy(n, cap, idx->g.W, idx->V, s);
+    if (st != LCP_OK) return st;
+    hipError_t e = hipSuccess;
+    if (c.sorted && N > 0) {
+        e = hipMemcpyAsync(n.sorted, c.sorted, (size_t)N * idx->g.W * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(n.perm, c.perm, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(n.A, c.A, (size_t)N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(n.bmin, c.bmin, (size_t)block_min_entries(N) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        const int levels = search_table_levels(N);
+        if (e == hipSuccess && levels > 0)
+            e = hipMemcpyAsync(n.stab, c.stab, (size_t)search_table_entries(levels) * sizeof(uint4),
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(n.dir, c.dir, ((size_t)idx->V + 2) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        n.release();
+        return fail(LCP_EDEVICE, "copying the sorted arrays: %s", hipGetErrorString(e));
+    }
+    c.release();
+    c = n;
+    return LCP_OK;
+}
+
+// Room for `rows` rows in the id-order rows and plane, both sorted copies and
+// the append temporaries, so that appends up to that size allocate nothing.
+lcp_status reserve_into(lcp_index* idx, int64_t rows, hipStream_t s) {
+    for (auto& kv : idx->ctx) HIP_TRY(hipStreamSynchronize(kv.first));
+    const int64_t N = idx->N;
+    const int W = idx->g.W;
+    if (idx->rows_cap < rows) {
+        uint32_t* nr = nullptr;
+        uint64_t* np = nullptr;
+        hipError_t e = hipMalloc(&nr, (size_t)rows * W * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&np, (size_t)plane_entries(rows) * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMemcpyAsync(nr, idx->d_rows, (size_t)N * W * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(np, idx->d_plane, (size_t)plane_entries(N) * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            if (nr) hipFree(nr);
+            if (np) hipFree(np);
+            return fail(e == hipErrorOutOfMemory ? LCP_ENOMEM : LCP_EDEVICE, "growing the rows: %s",
+                        hipGetErrorString(e));
+        }
+        hipFree(idx->d_rows);
+        hipFree(idx->d_plane);
+        idx->d_rows = nr;
+        idx->d_plane = np;
+        idx->rows_cap = rows;
+    }
+    lcp_status st = grow_copy(idx, idx->cp[idx->cur], rows, N, s);
+    if (st != LCP_OK) return st;
+    st = grow_copy(idx, idx->cp[idx->cur ^ 1], rows, 0, s);
+    if (st != LCP_OK) return st;
+    AppendScratch& a = idx->app;
+    if (!a.flag) {
+        HIP_TRY(hipMalloc(&a.flag, sizeof(uint32_t)));
+        HIP_TRY(hipHostMalloc(&a.flag_host, sizeof(uint32_t), hipHostMallocDefault));
+        HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(uint32_t), s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (a.cap < kRankSortMax) {
+        HIP_TRY(hipMalloc(&a.sorted, (size_t)kRankSortMax * W * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&a.lperm, (size_t)kRankSortMax * sizeof(int32_t)));
+        HIP_TRY(hipMalloc(&a.ub, (size_t)kRankSortMax * sizeof(int64_t)));
+        a.cap = kRankSortMax;
+    }
+    idx->generation += 1;  // the active arrays may have moved
+    return LCP_OK;
+}
 
 // Rows with ids N..N+n-1: the result equals a build over the concatenation.
 // The new rows are packed into the id-order rows after the old ones (and the
@@ -598,7 +709,9 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
     if (!a.flag) {
         HIP_TRY(hipMalloc(&a.flag, sizeof(uint32_t)));
         HIP_TRY(hipHostMalloc(&a.flag_host, sizeof(uint32_t), hipHostMallocDefault));
+        HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(uint32_t), s));
     }
+    const uint32_t epoch = ++a.epoch;  // a bad token raises the flag to this epoch: no clearing between appends
     if (n <= kRankSortMax) {
         if (a.cap < n) {
             if (a.sorted) hipFree(a.sorted);
@@ -613,8 +726,7 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
             HIP_TRY(hipMalloc(&a.ub, (size_t)kRankSortMax * sizeof(int64_t)));
             a.cap = kRankSortMax;
         }
-        HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(uint32_t), s));
-        HIP_TRY(launch_pack_keys(tokens, n, g, (uint32_t)idx->V, newkeys, a.flag, s));
+        HIP_TRY(launch_pack_keys(tokens, n, g, (uint32_t)idx->V, newkeys, a.flag, epoch, s));
         HIP_TRY(launch_rank_sort(newkeys, n, W, a.sorted, a.lperm, s));
         nsorted = a.sorted;
         nperm = a.lperm;
@@ -625,8 +737,7 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
         HIP_TRY(hipMalloc(&big.ub, (size_t)n * sizeof(int64_t)));
         lcp_status st = sort_rows(tokens, n, g, idx->V, s, newkeys, big.perm);
         if (st != LCP_OK) return st;  // index unchanged
-        HIP_TRY(launch_gather_rows(newkeys, big.perm, n, W, big.sorted, s));
-        HIP_TRY(hipMemsetAsync(a.flag, 0, sizeof(uint32_t), s));  // validated by sort_rows
+        HIP_TRY(launch_gather_rows(newkeys, big.perm, n, W, big.sorted, s));  // validated by sort_rows
         nsorted = big.sorted;
         nperm = big.perm;
         ub = big.ub;
@@ -636,12 +747,10 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
                                 dst.A, s));
     const int levels = search_table_levels(M);
     if (levels > 0) HIP_TRY(launch_search_tables(dst.sorted, M, W, levels, dst.stab, s));
-    HIP_TRY(launch_block_min(dst.perm, M, dst.bmin, s));
-    HIP_TRY(launch_first_token_dir(dst.sorted, M, g, idx->V, dst.dir, s));
-    HIP_TRY(launch_prefix_plane(rows, N, M, W, plane, s));
+    HIP_TRY(launch_append_tail(dst.perm, dst.sorted, M, g, idx->V, rows, N, dst.bmin, dst.dir, plane, s));
     HIP_TRY(hipMemcpyAsync(a.flag_host, a.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (*a.flag_host) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);  // index unchanged
+    if (*a.flag_host == epoch) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);  // index unchanged
 
     // commit
     if (fresh.rows) {
@@ -830,6 +939,15 @@ lcp_status lcp_index_views(const lcp_index* idx, const int32_t** perm, const uin
     return LCP_OK;
 }
 
+lcp_status lcp_index_reserve(lcp_index* idx, int64_t rows, void* stream) {
+    if (!idx) return fail(LCP_EINVAL, "index is NULL");
+    if (rows < 0 || rows > kMaxRows) return fail(LCP_EINVAL, "rows = %lld is outside [0, 2^31 - 2^16]", (long long)rows);
+    std::lock_guard<std::mutex> lk(idx->mu);
+    HIP_TRY(hipSetDevice(idx->device));
+    if (rows <= idx->N) rows = idx->N;
+    return reserve_into(idx, rows, static_cast<hipStream_t>(stream));
+}
+
 lcp_status lcp_index_set_search(lcp_index* idx, int32_t mode) {
     if (!idx) return fail(LCP_EINVAL, "index is NULL");
     if (mode != 0 && mode != 1) return fail(LCP_EINVAL, "search mode %d is not 0 or 1", mode);
@@ -837,6 +955,13 @@ lcp_status lcp_index_set_search(lcp_index* idx, int32_t mode) {
     for (auto& kv : idx->ctx) HIP_TRY(hipStreamSynchronize(kv.first));
     if (idx->search_mode != mode) idx->generation += 1;  // captured graphs hold the old view
     idx->search_mode = mode;
+    return LCP_OK;
+}
+
+lcp_status lcp_index_search_mode(const lcp_index* idx, int32_t* mode) {
+    if (!idx || !mode) return fail(LCP_EINVAL, "NULL index or output pointer");
+    std::lock_guard<std::mutex> lk(idx->mu);
+    *mode = idx->search_mode;
     return LCP_OK;
 }
 

@@ -17,9 +17,10 @@ namespace lcpx {
 
 // ------------------------------------------------------------ pack/validate
 
-// One thread per (row, key word): key-form row in id order + token range check.
+// One thread per (row, key word): key-form row in id order + token range check
+// (a token >= V raises *bad to at least `mark`).
 __global__ void k_pack_keys(const void* __restrict__ tokens, int64_t N, RowGeo g, uint32_t V,
-                            uint32_t* __restrict__ keys, uint32_t* __restrict__ bad) {
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ bad, uint32_t mark) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * g.W) return;
     const int64_t row = t / g.W;
@@ -38,7 +39,7 @@ __global__ void k_pack_keys(const void* __restrict__ tokens, int64_t N, RowGeo g
         x |= v << (32 - bits * (j + 1));
     }
     keys[t] = x;
-    if (out_of_range) atomicOr(bad, 1u);
+    if (out_of_range) atomicMax(bad, mark);
 }
 
 // One thread per (row, dense word): tokens at `dbits` bits each, concatenated
@@ -436,32 +437,40 @@ __global__ void k_upper_bounds(const uint32_t* __restrict__ sorted, int64_t N, c
 }
 
 // Stable sort of n new rows by rank: row j goes to position #{i : row i <
-// row j, or row i == row j and i < j}.  Each block stages tiles of the rows in
+// row j, or row i == row j and i < j}.  Rows are compared by their first two
+// key words as one 64-bit value (word 0 high), and by the remaining words only
+// where those agree.  Each block stages tiles of the rows' leading values in
 // LDS and every thread counts, for its own row, the rows of the tile ranked
-// before it.  O(n^2) row compares: used for small appends only.
-constexpr int kRankThreads = 256;
+// before it.  O(n^2) compares of one 64-bit value: used for small appends.
+constexpr int kRankThreads = 64;
+constexpr int kRankTile = 1024;
 __global__ __launch_bounds__(kRankThreads) void k_rank_sort(const uint32_t* __restrict__ keys, int64_t n, int W,
-                                                            int tile_rows, uint32_t* __restrict__ sorted,
+                                                            uint32_t* __restrict__ sorted,
                                                             int32_t* __restrict__ lperm) {
-    extern __shared__ uint32_t tile[];
+    __shared__ uint64_t tile[kRankTile];
     const int64_t j = (int64_t)blockIdx.x * kRankThreads + threadIdx.x;
     const bool act = j < n;
     const uint32_t* mine = keys + (act ? j : 0) * W;
+    const uint64_t pj = ((uint64_t)mine[0] << 32) | (W > 1 ? mine[1] : 0u);
     int64_t rank = 0;
-    for (int64_t t0 = 0; t0 < n; t0 += tile_rows) {
-        const int tn = (int)(n - t0 < tile_rows ? n - t0 : tile_rows);
+    for (int64_t t0 = 0; t0 < n; t0 += kRankTile) {
+        const int tn = (int)(n - t0 < kRankTile ? n - t0 : kRankTile);
         __syncthreads();
-        for (int e = threadIdx.x; e < tn * W; e += kRankThreads) tile[e] = keys[t0 * W + e];
+        for (int e = threadIdx.x; e < tn; e += kRankThreads) {
+            const uint32_t* o = keys + (t0 + e) * W;
+            tile[e] = ((uint64_t)o[0] << 32) | (W > 1 ? o[1] : 0u);
+        }
         __syncthreads();
         if (act) {
             for (int r = 0; r < tn; ++r) {
-                const uint32_t* o = tile + r * W;
-                int c = 0;
-                for (int w = 0; w < W && c == 0; ++w) {
-                    const uint32_t x = o[w], y = mine[w];
-                    c = x < y ? -1 : x > y ? 1 : 0;
+                const uint64_t pi = tile[r];
+                int c = pi < pj ? -1 : pi > pj ? 1 : 0;
+                const int64_t i = t0 + r;
+                if (c == 0 && i != j) {  // the leading words agree: the rest decides
+                    const uint32_t* o = keys + i * W;
+                    for (int w = 2; w < W && c == 0; ++w) c = o[w] < mine[w] ? -1 : o[w] > mine[w] ? 1 : 0;
                 }
-                rank += (c < 0 || (c == 0 && t0 + r < j)) ? 1 : 0;
+                rank += (c < 0 || (c == 0 && i < j)) ? 1 : 0;
             }
         }
     }
@@ -569,17 +578,63 @@ hipError_t launch_first_token_dir(const uint32_t* sorted, int64_t N, RowGeo g, i
     return hipGetLastError();
 }
 
+// The order-dependent summaries of a merged copy and the new rows' plane
+// entries in one launch: blocks [0, nb) take the tie summaries (a wave per 64
+// positions), the next nd blocks the first-token directory, the rest the plane.
+__global__ void k_append_tail(const int32_t* __restrict__ perm, const uint32_t* __restrict__ sorted, int64_t M,
+                              RowGeo g, int V, const uint32_t* __restrict__ rows, int64_t from,
+                              uint32_t* __restrict__ bmin, uint32_t* __restrict__ dir, uint64_t* __restrict__ plane,
+                              unsigned nb, unsigned nd) {
+    const unsigned b = blockIdx.x;
+    if (b < nb) {
+        const int64_t blk = (int64_t)b * (blockDim.x / kWave) + (threadIdx.x / kWave);
+        if (blk >= (M + kWave - 1) / kWave) return;  // whole waves leave together
+        const int64_t j = blk * kWave + lane_id();
+        const uint32_t v = wave_min_u32(j < M ? (uint32_t)perm[j] : 0xFFFFFFFFu);
+        if (lane_id() == 0) bmin[blk] = v;
+        return;
+    }
+    if (b < nb + nd) {
+        const int64_t t = (int64_t)(b - nb) * blockDim.x + threadIdx.x;
+        if (t > V + 1) return;
+        int64_t lo = 0, hi = M;
+        if (t >= V) lo = M;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if ((int64_t)(sorted[mid * g.W] >> (32 - 8 * g.tb)) < t)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        dir[t] = (uint32_t)lo;
+        return;
+    }
+    const int64_t i = from + (int64_t)(b - nb - nd) * blockDim.x + threadIdx.x;
+    if (i >= plane_entries(M)) return;
+    plane[i] = i < M ? ((uint64_t)rows[i * g.W] << 32) | (g.W > 1 ? rows[i * g.W + 1] : 0u) : 0ull;
+}
+
+hipError_t launch_append_tail(const int32_t* perm, const uint32_t* sorted, int64_t M, RowGeo g, int V,
+                              const uint32_t* rows, int64_t from, uint32_t* bmin, uint32_t* dir, uint64_t* plane,
+                              hipStream_t s) {
+    const unsigned nb = blocks_for(block_min_entries(M), 256 / kWave);
+    const unsigned nd = blocks_for((int64_t)V + 2, 256);
+    const int64_t np = plane_entries(M) - from;
+    const unsigned npb = np > 0 ? blocks_for(np, 256) : 0u;
+    hipLaunchKernelGGL(k_append_tail, dim3(nb + nd + npb), dim3(256), 0, s, perm, sorted, M, g, V, rows, from, bmin, dir,
+                       plane, nb, nd);
+    return hipGetLastError();
+}
+
 hipError_t launch_rank_sort(const uint32_t* keys, int64_t n, int W, uint32_t* sorted, int32_t* lperm, hipStream_t s) {
-    int tile = 8192 / W;  // 32 KB of LDS
-    if (tile > kRankThreads) tile = kRankThreads;
-    hipLaunchKernelGGL(k_rank_sort, dim3(blocks_for(n, kRankThreads)), dim3(kRankThreads),
-                       (size_t)tile * W * sizeof(uint32_t), s, keys, n, W, tile, sorted, lperm);
+    hipLaunchKernelGGL(k_rank_sort, dim3(blocks_for(n, kRankThreads)), dim3(kRankThreads), 0, s, keys, n, W, sorted,
+                       lperm);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_keys(const void* tokens, int64_t n, RowGeo g, uint32_t V, uint32_t* keys, uint32_t* bad,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_keys, dim3(blocks_for(n * g.W, 256)), dim3(256), 0, s, tokens, n, g, V, keys, bad);
+                            uint32_t mark, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_keys, dim3(blocks_for(n * g.W, 256)), dim3(256), 0, s, tokens, n, g, V, keys, bad, mark);
     return hipGetLastError();
 }
 
@@ -608,7 +663,7 @@ hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int le
 
 hipError_t launch_pack(const void* tokens, int64_t N, RowGeo g, uint32_t V, int dbits, int Wd, uint32_t* keys,
                        uint32_t* dense, uint32_t* bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_keys, dim3(blocks_for(N * g.W, 256)), dim3(256), 0, s, tokens, N, g, V, keys, bad);
+    hipLaunchKernelGGL(k_pack_keys, dim3(blocks_for(N * g.W, 256)), dim3(256), 0, s, tokens, N, g, V, keys, bad, 1u);
     hipLaunchKernelGGL(k_pack_dense, dim3(blocks_for(N * Wd, 256)), dim3(256), 0, s, tokens, N, g, dbits, Wd, dense);
     return hipGetLastError();
 }

@@ -35,7 +35,12 @@ hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, cons
 // key-form rows of n token rows (flag set on a token >= V), and their stable
 // order by rank (small n)
 hipError_t launch_pack_keys(const void* tokens, int64_t n, RowGeo g, uint32_t V, uint32_t* keys, uint32_t* bad,
-                            hipStream_t s);
+                            uint32_t mark, hipStream_t s);
+// after an append's merge: tie summaries and first-token directory of the
+// merged copy (M rows) and plane entries [from, plane_entries(M))
+hipError_t launch_append_tail(const int32_t* perm, const uint32_t* sorted, int64_t M, RowGeo g, int V,
+                              const uint32_t* rows, int64_t from, uint32_t* bmin, uint32_t* dir, uint64_t* plane,
+                              hipStream_t s);
 hipError_t launch_rank_sort(const uint32_t* keys, int64_t n, int W, uint32_t* sorted, int32_t* lperm, hipStream_t s);
 hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
                                 hipStream_t s);
@@ -129,6 +134,7 @@ hipError_t launch_index_query_persistent(const IndexView& ix, const QueryBatch& 
 // Full scan.  `part` must hold scan_partial_entries(...) keys.
 struct ScanPlan {
     int tq;             // queries per wave (a query group)
+    bool hash;          // the group's rows are pre-filtered by hash tables of its queries
     int nr;             // list registers (capacity 64*nr >= k_max)
     int chunks;         // row chunks (one wave each) over [seed_rows, N)
     int qgroups;        // query groups; each streams every row once

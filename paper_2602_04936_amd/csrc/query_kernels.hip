@@ -38,6 +38,7 @@ namespace lcpx {
 
 constexpr int kQueryWaves = 4;
 constexpr int kTieUnroll = 8;
+constexpr int kHeldUnroll = 10;  // tied ids held in registers: ranges of at most 640 rows
 constexpr int kFewTied = 16;  // tied selections of at most this many ids use repeated wave minima
 constexpr int kSelMax = kAdjWindow / 4;  // 32-bit entries of the LDS window the tie selections reuse
 
@@ -138,12 +139,13 @@ __device__ __forceinline__ void inner_by_rank(const IndexView& ix, uint8_t* win,
             }
 }
 
-// The m lowest ids among at most kTieUnroll*64 tied positions, 16 < m <=
-// kSelMax, whose ids the caller holds in `id` (0xFFFFFFFF past the range
-// end): the m-th smallest, tau, by bisection on the id bits from the most
-// significant (the ids are distinct, so exactly m of them are <= tau); those
-// m are compacted into the wave's LDS window and each is written at its rank,
-// the count of selected ids below it.
+// The m lowest ids among at most U*64 tied positions, m <= kSelMax, whose ids
+// the caller holds in `id` (0xFFFFFFFF past the range end): the m-th
+// smallest, tau, by bisection on the id bits from the most significant (the
+// ids are distinct, so exactly m of them are <= tau); those m are compacted
+// into the wave's LDS window and each is written at its rank, the count of
+// selected ids below it.
+template <int U>
 __device__ __forceinline__ void tied_select(const IndexView& ix, const uint32_t* id, int m, int c,
                                             int32_t* __restrict__ oid, int32_t* __restrict__ olc, uint32_t* sel) {
     const int lane = lane_id();
@@ -155,7 +157,7 @@ __device__ __forceinline__ void tied_select(const IndexView& ix, const uint32_t*
         const uint32_t want = pre << 1;
         int cnt = 0;
 #pragma unroll
-        for (int u = 0; u < kTieUnroll; ++u) cnt += popc64(ballot((id[u] >> b) == want));
+        for (int u = 0; u < U; ++u) cnt += popc64(ballot((id[u] >> b) == want));
         if (rem <= cnt) {
             pre = want;
         } else {
@@ -166,7 +168,7 @@ __device__ __forceinline__ void tied_select(const IndexView& ix, const uint32_t*
     const uint32_t tau = pre;
     int n = 0;
 #pragma unroll
-    for (int u = 0; u < kTieUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
         const bool s = id[u] <= tau;
         const uint64_t bal = ballot(s);
         const int pos = n + count_below(bal);
@@ -510,14 +512,15 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
     // overlaps the inner group's
     const int tnl = in_lo - l;
     const int tn = tnl + (r - in_hi);
-    const bool held = m > 0 && c > 0 && m <= kSelMax && tn <= kTieUnroll * kWave;
-    uint32_t tid[kTieUnroll];
+    const bool held = m > 0 && c > 0 && m <= kSelMax && tn <= kHeldUnroll * kWave;
+    const bool few = held && m <= kFewTied && tn <= kTieUnroll * kWave;
+    uint32_t tid[kHeldUnroll];
     {
         // positions fit in 32 bits (N < 2^31); t < tnl picks the left part
         const int tnl32 = tnl, tn32 = held ? tn : 0;
         const uint32_t lb = (uint32_t)l, rb = (uint32_t)in_hi - (uint32_t)tnl32;
 #pragma unroll
-        for (int u = 0; u < kTieUnroll; ++u) {
+        for (int u = 0; u < kHeldUnroll; ++u) {
             const int t = u * kWave + lane;
             const uint32_t j = (t < tnl32 ? lb : rb) + (uint32_t)t;
             tid[u] = t < tn32 ? (uint32_t)ix.perm[j] : 0xFFFFFFFFu;  // above every id
@@ -574,12 +577,12 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
 
     if (qb.stats != nullptr) {
         const bool pruned = m <= kSelMax && (in_lo - l) + (r - in_hi) >= kWave * 4 * (m > 8 ? m : 8);
-        const int path = m <= 0            ? kTieNone
-                         : c == 0          ? kTieIdWalk
-                         : held && m <= kFewTied ? kTieFew
-                         : held            ? kTieSelect
-                         : pruned          ? kTiePruned
-                                           : kTieList;
+        const int path = m <= 0   ? kTieNone
+                         : c == 0 ? kTieIdWalk
+                         : few    ? kTieFew
+                         : held   ? kTieSelect
+                         : pruned ? kTiePruned
+                                  : kTieList;
         if (lane == 0) *reinterpret_cast<int4*>(qb.stats + 4 * qi) = make_int4(c, n_gt, tn, path);
     }
 
@@ -600,7 +603,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 }
                 got += popc64(bal);
             }
-        } else if (held && m <= kFewTied) {
+        } else if (few) {
             // small case: each lane sorts its (at most 8) tied ids, then m
             // rounds take the wave minimum of the lanes' smallest remaining id
             // and the lane holding it drops that id
@@ -638,7 +641,7 @@ __device__ __forceinline__ void index_query_body(const IndexView& ix, const Quer
                 olc[n_gt + lane] = c;
             }
         } else if (held) {
-            tied_select(ix, tid, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
+            tied_select<kHeldUnroll>(ix, tid, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else if (m <= kSelMax && (in_lo - l) + (r - in_hi) >= kWave * 4 * (m > 8 ? m : 8)) {
             tied_pruned<NR>(ix, l, in_lo, in_hi, r, m, c, oid + n_gt, olc + n_gt, reinterpret_cast<uint32_t*>(win));
         } else {

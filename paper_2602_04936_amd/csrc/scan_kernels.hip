@@ -188,11 +188,21 @@ struct ScanGrid {
 // Consecutive blocks (after the XCD remap below) take the same rows for
 // different query groups, so a chunk is fetched into one XCD's L2 once.
 //
-// Code layout: the unrolled hot loop only tests, per query, whether any of the
-// step's rows passes its filter (one 64-bit compare per row, and two ANDs
-// when the filter keeps part of the 64 bits), and sets one bit per flagged
-// query; a single non-unrolled slow path then serves the flagged queries with
-// the query's list and filter in LDS.
+// Which rows need a closer look is decided in two ways:
+//  - a hash pre-filter (the hashed variants, for large groups): the block puts each
+//    query's filter at its starting limit (a looser filter than any the waves
+//    reach later) into one of two small hash tables in LDS, one per mask
+//    length, keyed by the masked query value; per row and table the hot loop
+//    costs one hash, one LDS read and two 64-bit compares however many
+//    queries the table holds, and a step with a hit tests its queries one by
+//    one.  Queries that do not fit (a third mask length, a full slot, no
+//    limit) are tested one by one on every step;
+//  - one by one: the query's current filter (lane i holds query i's) against
+//    the step's rows, one 64-bit compare per row, and two ANDs when the
+//    filter keeps part of the 64 bits.
+// Both only select candidates: a flagged query's rows are re-tested against
+// its current filter in the slow path, which computes exact LCPs and offers
+// them to the query's list in LDS.
 //
 // At the end each wave appends, per query, the entries of its list that do
 // not exceed the query's limit to the query's partial list (cap entries at
@@ -202,14 +212,33 @@ constexpr int kScanU = 4;                                  // 16-byte loads per 
 constexpr int64_t kPairRows = 2 * kWave;                   // rows of one 16-byte load of the wave
 constexpr int64_t kScanStepRows = kScanU * kPairRows;      // rows per wave step
 constexpr int kGthrEvery = 4;                              // steps between pick-ups of shared limits
+constexpr int kHashTables = 2;
+constexpr int kHashSlots = 128;                            // two keys each
+constexpr uint64_t kHashEmpty = ~0ull;                     // an empty slot's keys (a row equal to it only costs a test)
 
-template <int NR, int TQ>
+// Block-shared pre-filter state in LDS.
+struct ScanHash {
+    uint4 slot[kHashTables][kHashSlots];  // (key0 lo, key0 hi, key1 lo, key1 hi)
+    uint32_t fill[kHashTables][kHashSlots];
+    uint64_t mask[kHashTables];
+    uint64_t left;  // queries tested one by one on every step
+    int32_t ntab;
+    int32_t pad_;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
+    const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+    const uint32_t x = hi ^ lo ^ (hi >> 16);
+    return (__umul24(x & 0xFFFFFFu, 0x9E3779u) >> 13) & (kHashSlots - 1);
+}
+
+template <int NR, int TQ, bool kHash>
 __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, QueryBatch qb,
                                                              const uint32_t* __restrict__ qkeys, ScanGrid sg,
                                                              int64_t cap, uint64_t* __restrict__ part,
                                                              uint32_t* __restrict__ cnt,
                                                              uint64_t* __restrict__ gthr) {
-    static_assert(TQ <= 64, "one flag bit per query");
+    static_assert(TQ <= 64, "one lane and one flag bit per query");
     extern __shared__ uint64_t s_dyn64[];
     const RowGeo g = ix.g;
     const int W = g.W;
@@ -221,29 +250,98 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     const unsigned xcd = b & 7u, q8 = nb >> 3, r8 = nb & 7u;
     const unsigned lb = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + (b >> 3);
     const int grp = (int)(lb % (unsigned)sg.qgroups);
-    const int pidx = (int)(lb / (unsigned)sg.qgroups) * kScanWaves + wv;
+    const int pidx0 = (int)(lb / (unsigned)sg.qgroups) * kScanWaves;
+    const int pidx = pidx0 + wv;
     const int64_t q0i = (int64_t)grp * TQ;
     const int ntq = (int)(qb.Q - q0i < TQ ? qb.Q - q0i : TQ);
+    const uint64_t real = ntq >= 64 ? ~0ull : (1ull << ntq) - 1;
+    const int64_t N = ix.N;
 
-    uint32_t* s_q = reinterpret_cast<uint32_t*>(s_dyn64);  // [TQ][W] query words, shared by the block
-    const int qwords64 = (TQ * W + 1) / 2;
-    ScanFilter* filt = reinterpret_cast<ScanFilter*>(s_dyn64 + qwords64) + wv * TQ;
-    uint64_t* lists = s_dyn64 + qwords64 + (size_t)kScanWaves * TQ * (sizeof(ScanFilter) / 8) +
+    auto chunk_lo = [&](int pi) -> int64_t {
+        return pi < sg.seed_chunks ? (int64_t)pi * sg.seed_chunk_rows
+                                   : sg.seed_rows + (int64_t)(pi - sg.seed_chunks) * sg.chunk_rows;
+    };
+
+    // LDS: [TQ][W] query words, the pre-filter (hashed variants), then per
+    // wave [TQ] filters and [TQ][lstride] list entries
+    uint32_t* s_q = reinterpret_cast<uint32_t*>(s_dyn64);
+    const int qwords64 = (TQ * W + 3) / 4 * 2;  // 16-byte aligned
+    ScanHash* hs = reinterpret_cast<ScanHash*>(s_dyn64 + qwords64);
+    const int hash64 = kHash ? (int)(sizeof(ScanHash) / 8) : 0;
+    ScanFilter* filt = reinterpret_cast<ScanFilter*>(s_dyn64 + qwords64 + hash64) + wv * TQ;
+    uint64_t* lists = s_dyn64 + qwords64 + hash64 + (size_t)kScanWaves * TQ * (sizeof(ScanFilter) / 8) +
                       (size_t)wv * TQ * sg.lstride;
     for (int t = threadIdx.x; t < TQ * W; t += kScanWaves * kWave)
         s_q[t] = t < ntq * W ? qkeys[q0i * W + t] : 0u;
+    if constexpr (kHash) {
+        for (int t = threadIdx.x; t < kHashTables * kHashSlots; t += kScanWaves * kWave) {
+            (&hs->slot[0][0])[t] = make_uint4(~0u, ~0u, ~0u, ~0u);
+            (&hs->fill[0][0])[t] = 0u;
+        }
+    }
     __syncthreads();
+    if constexpr (kHash) {
+        if (wv == 0) {
+            // the filters at the starting limits, for the rows from the
+            // block's first chunk on (the loosest any of its waves uses)
+            uint64_t msk = 0, qm = 1;
+            if (lane < ntq) {
+                const uint32_t* q = s_q + lane * W;
+                const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
+                limit_filter(gthr[q0i + lane], chunk_lo(pidx0), q01, g, msk, qm);
+            }
+            // up to two mask lengths get a table; a query without a limit
+            // (mask 0) or with another mask length is tested one by one
+            const bool cand = lane < ntq && msk != 0;
+            int tab = -1;
+            uint64_t m0 = 0, m1 = 0;
+            uint64_t pend = ballot(cand);
+            int ntab = 0;
+            if (pend) {
+                m0 = readlane64(msk, low_lane(pend));
+                tab = cand && msk == m0 ? 0 : tab;
+                ntab = 1;
+                pend &= ~ballot(cand && msk == m0);
+                if (pend) {
+                    m1 = readlane64(msk, low_lane(pend));
+                    tab = cand && msk == m1 ? 1 : tab;
+                    ntab = 2;
+                }
+            }
+            // claim a place in the slot: the first key of a slot also fills
+            // its second place, a second key then overwrites that place
+            uint32_t sl = tab >= 0 ? hash_slot(qm) : 0u;
+            uint32_t pos = 2;
+            if (tab >= 0) pos = atomicAdd(&hs->fill[tab][sl], 1u);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (pos == 0) hs->slot[tab][sl] = make_uint4((uint32_t)qm, (uint32_t)(qm >> 32), (uint32_t)qm,
+                                                         (uint32_t)(qm >> 32));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (pos == 1) {
+                hs->slot[tab][sl].z = (uint32_t)qm;
+                hs->slot[tab][sl].w = (uint32_t)(qm >> 32);
+            }
+            const uint64_t left = ballot(lane < ntq && pos >= 2);
+            if (lane == 0) {
+                hs->mask[0] = m0;
+                hs->mask[1] = m1;
+                hs->ntab = ntab;
+                hs->left = left;
+            }
+        }
+        __syncthreads();
+    }
     if (pidx >= sg.nparts) return;
 
-    const int64_t N = ix.N;
-    int64_t r_lo, r_hi;
-    if (pidx < sg.seed_chunks) {
-        r_lo = (int64_t)pidx * sg.seed_chunk_rows;
+    int64_t r_lo = chunk_lo(pidx), r_hi;
+    if (pidx < sg.seed_chunks)
         r_hi = r_lo + sg.seed_chunk_rows < sg.seed_rows ? r_lo + sg.seed_chunk_rows : sg.seed_rows;
-    } else {
-        r_lo = sg.seed_rows + (int64_t)(pidx - sg.seed_chunks) * sg.chunk_rows;
+    else
         r_hi = r_lo + sg.chunk_rows < N ? r_lo + sg.chunk_rows : N;
-    }
     // pairs of rows [p_lo, p_hi): r_lo is even, and an odd N has a zero entry
     // after its last row; loads past the chunk re-read its last pair.  The
     // first step's loads go out before the filters are set up.
@@ -255,19 +353,19 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         const int64_t pp = p_lo + u * kWave + lane;
         nx[u] = pl[pp < p_last ? pp : p_last];
     }
-    // filters from the starting limits; query slots past the batch get one
-    // that nothing matches
+    // the wave's filters from the starting limits; query slots past the batch
+    // get one that nothing matches
     if (lane < TQ) {
         ScanFilter f;
-        const bool real = lane < ntq;
-        f.lim = real ? gthr[q0i + lane] : kKeyMax;
-        const int ki = real ? query_k(qb, q0i + lane) : 1;
+        const bool is_real = lane < ntq;
+        f.lim = is_real ? gthr[q0i + lane] : kKeyMax;
+        const int ki = is_real ? query_k(qb, q0i + lane) : 1;
         f.kk = (int)((int64_t)ki < N ? (int64_t)ki : N);
         f.pad_ = 0;
         const uint32_t* q = s_q + lane * W;
         const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
         limit_filter(f.lim, r_lo, q01, g, f.msk, f.qm);
-        if (!real) {
+        if (!is_real) {
             f.msk = 0;
             f.qm = 1;
         }
@@ -278,23 +376,33 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // the filters as wave-uniform values (scalar registers), reloaded from
-    // LDS only after the slow path or a pick-up of shared limits changed one
-    uint64_t fm[TQ], fq[TQ];
+    // lane i holds query i's current filter; reloaded after any change
+    uint64_t lm = 0, lq = 1;
     auto load_filters = [&]() {
-#pragma unroll
-        for (int i = 0; i < TQ; ++i) {
-            fm[i] = uniform64(filt[i].msk);
-            fq[i] = uniform64(filt[i].qm);
+        if (lane < TQ) {
+            lm = filt[lane].msk;
+            lq = filt[lane].qm;
         }
     };
     load_filters();
+    uint64_t hmask[kHashTables] = {0, 0};
+    int ntab = 0;
+    uint64_t one_by_one = real;
+    if constexpr (kHash) {
+        hmask[0] = uniform64(hs->mask[0]);
+        hmask[1] = uniform64(hs->mask[1]);
+        ntab = (int)uniform((uint32_t)hs->ntab);
+        one_by_one = uniform64(hs->left) & real;
+    }
+    const uint64_t hashed = real & ~one_by_one;
+
     int it = 0;
     for (int64_t base = r_lo; base < r_hi; base += kScanStepRows, ++it) {
         if (it > 0 && it % kGthrEvery == 0) {
             // pick up tighter limits reached by other waves: lane i reads query
             // i's limit with a plain load (a stale value only prunes less)
             const uint64_t mine = lane < ntq ? gthr[q0i + lane] : kKeyMax;
+            bool changed = false;
 #pragma unroll 1
             for (int i = 0; i < ntq; ++i) {
                 const uint64_t gv = readlane64(mine, i);
@@ -308,12 +416,15 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                         filt[i].msk = msk;
                         filt[i].qm = qm;
                     }
+                    changed = true;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            load_filters();
+            if (changed) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                load_filters();
+            }
         }
         // the step's rows, as 64-bit plane values (word 0 high): row
         // base + u * 128 + 2 * lane + h is v[2u + h]
@@ -331,13 +442,31 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                 nx[u] = pl[pp < p_last ? pp : p_last];
             }
         }
-        // hot loop: which queries have a row passing their filter this step.
-        // Lanes past the chunk re-read its last pair, so they may flag a
-        // query; the slow path drops them.
-        uint64_t flagged = 0;
+        // which queries have a row passing their filter this step.  Lanes
+        // past the chunk re-read its last pair, so they may flag a query; the
+        // slow path drops them.
+        uint64_t test = one_by_one;
+        if constexpr (kHash) {
+            uint64_t hit = 0;
+#pragma unroll 1
+            for (int t0 = 0; t0 < ntab; ++t0) {
+                const uint64_t m = hmask[t0];
+                const uint4* tab = hs->slot[t0];
 #pragma unroll
-        for (int i = 0; i < TQ; ++i) {
-            const uint64_t msk = fm[i], qm = fq[i];
+                for (int t = 0; t < 2 * kScanU; ++t) {
+                    const uint64_t key = m == ~0ull ? v[t] : v[t] & m;
+                    const uint4 e = tab[hash_slot(key)];
+                    const uint64_t k0 = ((uint64_t)e.y << 32) | e.x, k1 = ((uint64_t)e.w << 32) | e.z;
+                    hit |= ballot(key == k0 || key == k1);
+                }
+            }
+            if (hit) test |= hashed;
+        }
+        uint64_t flagged = 0;
+#pragma unroll 1
+        for (uint64_t todo = test; todo; todo &= todo - 1) {
+            const int i = low_lane(todo);
+            const uint64_t msk = readlane64(lm, i), qm = readlane64(lq, i);
             uint64_t any = 0;
             if (msk == ~0ull) {
 #pragma unroll
@@ -555,28 +684,40 @@ static int nr_for(int32_t k_max) { return k_max <= 64 ? 1 : k_max <= 128 ? 2 : k
 
 // Bytes of LDS a scan block needs: the query words, then per wave TQ filters
 // and TQ lists of k_max entries.
-static size_t scan_block_lds(int tq, int32_t k_max, int W) {
-    return ((size_t)tq * W * sizeof(uint32_t) + 7) / 8 * 8 +
+static size_t scan_block_lds(int tq, bool hash, int32_t k_max, int W) {
+    return ((size_t)tq * W * sizeof(uint32_t) + 15) / 16 * 16 + (hash ? sizeof(ScanHash) : 0) +
            (size_t)kScanWaves * tq * (sizeof(ScanFilter) + (size_t)k_max * sizeof(uint64_t));
 }
 constexpr size_t kScanLdsBudget = 40 << 10;  // per block: at least 4 blocks (16 waves) per CU
 
-// Queries per wave, from the compiled set for the list size: the fewest
-// (query slot, row) tests for the batch, then the most queries per wave,
-// within the LDS budget (one query per wave always fits).
-static int tq_for(int nr, int32_t k_max, int64_t Q, int W) {
-    static const int c1[] = {16, 8, 2, 1}, c2[] = {8, 1}, c4[] = {4, 1}, c16[] = {1};
-    const int* c = nr == 1 ? c1 : nr == 2 ? c2 : nr == 4 ? c4 : c16;
-    const int n = nr == 1 ? 4 : nr == 16 ? 1 : 2;
-    int best = 1;
-    int64_t best_slots = Q;
+// Queries per wave, from the compiled set for the list size and within the
+// LDS budget (one query per wave always fits): the least test work per row
+// over the query groups, a larger group on ties.  A group tested one query at
+// a time costs one compare per real query; a hashed group costs, whatever its
+// size, about kHashCost compares (measured on the 2M- and 8M-row hierarchy
+// databases: its random LDS reads and its registers, 108 against 75, make the
+// hashed variant slower at 32 queries and faster from a few hundred on).
+constexpr int kHashCost = 48;
+struct ScanShape {
+    int tq;
+    bool hash;
+};
+static ScanShape shape_for(int nr, int32_t k_max, int64_t Q, int W) {
+    static const ScanShape c1[] = {{64, true}, {16, false}, {8, false}, {2, false}, {1, false}},
+                           c2[] = {{16, true}, {8, false}, {1, false}}, c4[] = {{4, false}, {1, false}},
+                           c16[] = {{1, false}};
+    const ScanShape* c = nr == 1 ? c1 : nr == 2 ? c2 : nr == 4 ? c4 : c16;
+    const int n = nr == 1 ? 5 : nr == 2 ? 3 : nr == 4 ? 2 : 1;
+    ScanShape best = {1, false};
+    int64_t best_cost = Q;
     for (int i = n - 1; i >= 0; --i) {  // ascending tq: a larger one wins ties
-        const int tq = c[i];
-        if (tq > 1 && scan_block_lds(tq, k_max, W) > kScanLdsBudget) continue;
-        const int64_t slots = (Q + tq - 1) / tq * tq;
-        if (slots <= best_slots) {
-            best = tq;
-            best_slots = slots;
+        const ScanShape sh = c[i];
+        if (sh.tq > 1 && scan_block_lds(sh.tq, sh.hash, k_max, W) > kScanLdsBudget) continue;
+        const int64_t groups = (Q + sh.tq - 1) / sh.tq;
+        const int64_t cost = groups * (sh.hash ? kHashCost : (Q < sh.tq ? Q : sh.tq));
+        if (cost <= best_cost) {
+            best = sh;
+            best_cost = cost;
         }
     }
     return best;
@@ -590,7 +731,9 @@ constexpr int64_t kScanTargetWaves = 8192;  // 32 per CU
 ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budget_bytes) {
     ScanPlan p;
     p.nr = nr_for(k_max);
-    p.tq = tq_for(p.nr, k_max, Q, W);
+    const ScanShape sh = shape_for(p.nr, k_max, Q, W);
+    p.tq = sh.tq;
+    p.hash = sh.hash;
     p.qgroups = (int)((Q + p.tq - 1) / p.tq);
     // the sample: 65,536 rows, and for batches of at most 1,024 queries up to
     // 1/32 of a larger database (at most 262,144 rows), so that the starting
@@ -665,7 +808,7 @@ size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, const R
     return (scan_scratch(p, Q, k_max, g, nullptr).words + 1) / 2;
 }
 
-template <int NR, int TQ>
+template <int NR, int TQ, bool H>
 static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, const ScanScratch& sc,
                           int32_t k_max, hipStream_t s) {
     ScanGrid sg;
@@ -676,9 +819,9 @@ static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanP
     sg.seed_chunks = p.seed_chunks;
     sg.qgroups = p.qgroups;
     sg.lstride = k_max;
-    const size_t shm = scan_block_lds(TQ, k_max, ix.g.W);
+    const size_t shm = scan_block_lds(TQ, H, k_max, ix.g.W);
     const int64_t blocks = (int64_t)p.qgroups * ((p.nparts + kScanWaves - 1) / kScanWaves);
-    hipLaunchKernelGGL((k_scan<NR, TQ>), dim3((unsigned)blocks), dim3(kScanWaves * kWave), shm, s, ix, qb, sc.qkeys,
+    hipLaunchKernelGGL((k_scan<NR, TQ, H>), dim3((unsigned)blocks), dim3(kScanWaves * kWave), shm, s, ix, qb, sc.qkeys,
                        sg, sc.cap, sc.part, sc.cnt, sc.gthr);
 }
 
@@ -695,16 +838,18 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
     hipLaunchKernelGGL(k_seed_limit, dim3((unsigned)((qb.Q + kScanWaves - 1) / kScanWaves)), dim3(kScanWaves * kWave),
                        0, s, qb, ix.N, ix.g.L, p.seed_rows, sc.hist, sc.gthr);
     if (ev0) hipEventRecord(ev0, s);
-    switch (p.nr * 100 + p.tq) {
-        case 116: launch_scan_t<1, 16>(ix, qb, p, sc, qb.k_max, s); break;
-        case 108: launch_scan_t<1, 8>(ix, qb, p, sc, qb.k_max, s); break;
-        case 102: launch_scan_t<1, 2>(ix, qb, p, sc, qb.k_max, s); break;
-        case 101: launch_scan_t<1, 1>(ix, qb, p, sc, qb.k_max, s); break;
-        case 208: launch_scan_t<2, 8>(ix, qb, p, sc, qb.k_max, s); break;
-        case 201: launch_scan_t<2, 1>(ix, qb, p, sc, qb.k_max, s); break;
-        case 404: launch_scan_t<4, 4>(ix, qb, p, sc, qb.k_max, s); break;
-        case 401: launch_scan_t<4, 1>(ix, qb, p, sc, qb.k_max, s); break;
-        case 1601: launch_scan_t<16, 1>(ix, qb, p, sc, qb.k_max, s); break;
+    switch (p.nr * 1000 + p.tq * 10 + (p.hash ? 1 : 0)) {
+        case 1641: launch_scan_t<1, 64, true>(ix, qb, p, sc, qb.k_max, s); break;
+        case 1160: launch_scan_t<1, 16, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 1080: launch_scan_t<1, 8, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 1020: launch_scan_t<1, 2, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 1010: launch_scan_t<1, 1, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 2161: launch_scan_t<2, 16, true>(ix, qb, p, sc, qb.k_max, s); break;
+        case 2080: launch_scan_t<2, 8, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 2010: launch_scan_t<2, 1, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 4040: launch_scan_t<4, 4, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 4010: launch_scan_t<4, 1, false>(ix, qb, p, sc, qb.k_max, s); break;
+        case 16010: launch_scan_t<16, 1, false>(ix, qb, p, sc, qb.k_max, s); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

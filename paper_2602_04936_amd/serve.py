@@ -356,7 +356,8 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
     benchmark": each step queries the current readings of every sensor).
 
     steps        : iterable of [S, L] token arrays, one batch per step
-    rate_hz      : target step rate; step t is released at t / rate_hz
+    rate_hz      : target step rate; step t is released at t / rate_hz (None or
+                   0: unpaced, each step released when the previous one is done)
     append_every : every that many steps, `append(index, batch)` is called with
                    the step's batch and must return the index to use next
                    (rows join the database with the next ids)
@@ -376,9 +377,12 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
     t0 = time.perf_counter()
     n = 0
     for t, batch in enumerate(steps):
-        release = t / rate_hz
-        while time.perf_counter() - t0 < release:
-            pass
+        if rate_hz:
+            release = t / rate_hz
+            while time.perf_counter() - t0 < release:
+                pass
+        else:  # unpaced: each step is released when the previous one is done
+            release = time.perf_counter() - t0
         raw = np.ascontiguousarray(batch if batch.dtype != np.uint16 else batch.view(np.int16))
         if buf.get("shape") != raw.shape:  # pinned staging and outputs, reused across steps
             qdt = torch.uint8 if raw.dtype == np.uint8 else torch.int16
@@ -418,6 +422,7 @@ def run_step_stream(index, steps, rate_hz: float, k: int, append_every: int = 0,
         "max_step_ms": round(float(lat.max()), 4),
         "appends": len(appends_ms),
         "append_ms_mean": round(float(np.mean(appends_ms)), 3) if appends_ms else None,
+        "append_ms": [round(x, 3) for x in appends_ms],
         "index": index,
         **({"answers": kept} if keep is not None else {}),
     }

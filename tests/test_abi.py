@@ -65,6 +65,18 @@ def test_error_paths_without_gpu():
     lib.lcp_index_append.restype = ctypes.c_int
     lib.lcp_index_append.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     assert lib.lcp_index_append(None, None, 1, None) == -1
+    lib.lcp_index_reserve.restype = ctypes.c_int
+    lib.lcp_index_reserve.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    assert lib.lcp_index_reserve(None, 10, None) == -1
+    lib.lcp_index_set_search.restype = ctypes.c_int
+    lib.lcp_index_set_search.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    assert lib.lcp_index_set_search(None, 1) == -1
+    lib.lcp_index_generation.restype = ctypes.c_int
+    lib.lcp_index_generation.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.lcp_index_generation(None, None) == -1
+    lib.lcp_topk_stats.restype = ctypes.c_int
+    lib.lcp_topk_stats.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] + [ctypes.c_void_p] * 5
+    assert lib.lcp_topk_stats(None, None, 1, None, None, None, None, None) == -1
     lib.lcp_index_free(None)
 
 

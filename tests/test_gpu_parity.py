@@ -303,13 +303,14 @@ def _tie_case(rng, T, n_gt, n_other=300, L=6):
 @pytest.mark.parametrize("T,n_gt,k", [
     (512, 0, 16), (512, 0, 17), (512, 3, 259), (513, 0, 17), (512, 0, 257), (64, 0, 64),
     (3000, 2, 12), (20000, 5, 200), (60000, 5, 200), (200, 127, 128), (200, 63, 64), (200, 64, 66),
-    (511, 120, 128), (64, 0, 16), (65, 2, 16), (128, 0, 10), (129, 3, 12)])
+    (511, 120, 128), (64, 0, 16), (65, 2, 16), (128, 0, 10), (129, 3, 12),
+    (513, 0, 1), (600, 0, 10), (640, 3, 16), (640, 0, 200), (641, 0, 10), (641, 2, 17)])
 def test_tie_selection_boundaries(P, T, n_gt, k):
     """Each tie-selection path at its limits: wave minima (m <= 16, <= 512
-    tied rows, also at 64 and 128 rows), bisection select (m <= 256, <= 512
-    rows), pruned by block
-    minima (long ranges), the sorted list otherwise; inner groups of up to
-    127 rows ranked by counting."""
+    tied rows, also at 64 and 128 rows), bisection select (m <= 256 from at
+    most 640 rows, and m <= 16 from 513 to 640 rows), pruned by block minima
+    (long ranges), the sorted list otherwise; inner groups of up to 127 rows
+    ranked by counting."""
     rng = np.random.default_rng(T * 1000 + n_gt * 7 + k)
     db, q = _tie_case(rng, T, n_gt)
     c, above, tn = _tie_shape(db, q[0], k)
@@ -619,9 +620,80 @@ def test_first_token_directory_search(P, case):
     wi, wl, _ = oracle.c_topk(db, qs, ks)
     with P.Index(db, V) as idx:
         g0 = idx.generation()
+        switches, cur = 0, idx.search_mode()
         for mode in (0, 1, 0):
             idx.set_search(mode)
+            switches += mode != cur
+            cur = mode
+            assert idx.search_mode() == mode
             r = idx.topk(qs, ks)
             torch.cuda.synchronize()
             assert (r.ids.cpu().numpy() == wi).all() and (r.lcps.cpu().numpy() == wl).all(), (case, mode)
-        assert idx.generation() == g0 + 2
+        assert idx.generation() == g0 + switches
+
+
+def test_reserve_then_appends_equal_a_rebuild(P):
+    """After lcp_index_reserve, appends up to the reserved size leave an index
+    equal to a build over all rows; the generation counts the reserve and
+    every append."""
+    import torch
+    st = synth.SensorStream(seed=91, sensors=300)
+    hist = np.concatenate(list(st.steps(40)), axis=0)
+    with P.Index(hist, 16) as idx:
+        g0 = idx.generation()
+        idx.reserve(idx.N + 5 * 300)
+        assert idx.generation() == g0 + 1
+        rows = [hist]
+        for _ in range(5):
+            b = st.step()
+            idx.append(b)
+            rows.append(b)
+        assert idx.generation() == g0 + 6
+        whole = np.concatenate(rows)
+        va = {k: v.cpu().numpy() for k, v in idx.views().items()}
+        qs = st.step()
+        r = idx.topk(qs, 5)
+        torch.cuda.synchronize()
+    with P.Index(whole, 16) as ref:
+        vb = {k: v.cpu().numpy() for k, v in ref.views().items()}
+    for key in ("perm", "adj_lcp", "sorted_keys", "id_keys"):
+        assert (va[key] == vb[key]).all(), key
+    wi, wl, _ = oracle.c_topk(whole, qs, 5)
+    assert (r.ids.cpu().numpy() == wi).all() and (r.lcps.cpu().numpy() == wl).all()
+
+
+def test_build_picks_the_search_with_fewer_steps(P):
+    """c2-like rows (first tokens spread over 256 values, buckets of about
+    2,000 rows) take the directory; the c3 hierarchy (16 first tokens, buckets
+    of 125,000 rows) keeps the search tables."""
+    rng = np.random.default_rng(5)
+    db = synth.prototype_rows(rng, synth.random_rows(rng, 4096, 64, 256), 500_000, 0.05, 256)
+    with P.Index(db, 256) as idx:
+        assert idx.search_mode() == 1
+    w = synth.c3_like(2_000_000, 8, seed=20)
+    with P.Index(w.db, w.V) as idx:
+        assert idx.search_mode() == 0
+
+
+@pytest.mark.parametrize("L,V", [(12, 16), (9, 300)])
+def test_append_rows_equal_in_their_first_bytes(P, L, V):
+    """Appended rows that agree on their first 8 bytes and differ later, and
+    exact duplicates within the batch and of old rows, sort as a rebuild
+    does (ties by id)."""
+    import torch
+    rng = np.random.default_rng(L * 1000 + V)
+    old = synth.random_rows(rng, 4000, L, V)
+    base = synth.random_rows(rng, 1, L, V)
+    same_head = np.repeat(base, 600, axis=0)
+    same_head[:, L - 3:] = synth.random_rows(rng, 600, 3, V)  # only the last 3 tokens differ
+    batch = np.concatenate([same_head, same_head[:50], old[:40], same_head[::7]])
+    batch = batch[rng.permutation(batch.shape[0])]
+    whole = np.concatenate([old, batch])
+    with P.Index(old, V) as idx:
+        idx.append(batch)
+        va = {k: v.cpu().numpy() for k, v in idx.views().items()}
+    with P.Index(whole, V) as ref:
+        vb = {k: v.cpu().numpy() for k, v in ref.views().items()}
+    for key in ("perm", "adj_lcp", "sorted_keys", "id_keys"):
+        assert (va[key] == vb[key]).all(), key
+    assert (va["perm"] == O.sorted_permutation(whole)).all()
