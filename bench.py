@@ -211,11 +211,14 @@ def main():
     idx.kernel_time(2)
     idx.set_kernel_timing(False)
     row_bytes = w.L * 2
-    passes_bw = idx.scan_info(nbw, args.k)[0]
+    groups_bw = idx.scan_info(nbw, args.k)[0]
     # the pass streams the 8-byte prefix plane (key words 0-1 of every row);
-    # whole rows are read only for rows that tie on those 8 bytes
+    # whole rows are read only for rows that tie on those 8 bytes.  Each query
+    # group streams the plane, but the groups' blocks take the same rows at
+    # the same time on one XCD, so HBM sees one pass (the FETCH_SIZE counter
+    # agrees): the bytes charged are one pass plus the query rows
     plane_bytes = 8
-    bw_bytes = w.N * plane_bytes * passes_bw + nbw * row_bytes
+    bw_bytes = w.N * plane_bytes + nbw * row_bytes
     bw_gbs = bw_bytes / (bw_ms / bw_n * 1e-3) / 1e9
 
     # ---- the same Q=32 pass with the 256 MB Infinity Cache flushed before each
@@ -294,7 +297,8 @@ def main():
         lidx.set_kernel_timing(False)
         l_pass_us = lm / max(ln, 1) * 1e3
         l_cold_us = cold_pass(lidx, lq[:32], args.k, lbw, False)
-        l_passes = lidx.scan_info(32, args.k)[0]
+        l_groups = lidx.scan_info(32, args.k)[0]
+        l_bytes = wl.N * plane_bytes + 32 * row_bytes
         t = time.perf_counter()
         for _ in range(2):
             lidx.scan_topk(lq, args.k, out=lo[0])
@@ -304,12 +308,12 @@ def main():
                  "index_qps": round(l_qps, 1), "index_ms_per_step": round(wl.Q / l_qps * 1e3, 5),
                  "scan_qps": round(l_scan_qps, 1),
                  "scan_pass_q32_us": round(l_pass_us, 2),
-                 "scan_pass_q32_plane_GBps": round(wl.N * plane_bytes * l_passes / (l_pass_us * 1e-6) / 1e9, 1),
+                 "scan_pass_q32_GBps": round(l_bytes / (l_pass_us * 1e-6) / 1e9, 1),
                  "scan_pass_q32_cold_us": round(l_cold_us, 2),
-                 "scan_pass_q32_cold_plane_GBps": round(wl.N * plane_bytes * l_passes / (l_cold_us * 1e-6) / 1e9, 1),
-                 "scan_pass_q32_cold_frac": round(wl.N * plane_bytes * l_passes / (l_cold_us * 1e-6) / 1e9 /
-                                                  HBM_PEAK_GBS, 4),
-                 "passes_over_db_q32": l_passes,
+                 "scan_pass_q32_cold_GBps": round(l_bytes / (l_cold_us * 1e-6) / 1e9, 1),
+                 "scan_pass_q32_cold_frac": round(l_bytes / (l_cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                 "scan_pass_q32_bytes": int(l_bytes),
+                 "query_groups_q32": l_groups,
                  "streaming_reference_torch_sum": stream_reference(wl.N * plane_bytes)}
         lidx.close()
         del wl, lq, lo
@@ -337,8 +341,8 @@ def main():
     idx_bytes = shape.pop("algorithmic_bytes_per_launch")
     idx_gbs = idx_bytes / (k_avg_ms * 1e-3) / 1e9
     scan_kernel_ms = s_ms / max(s_n, 1)
-    passes = idx.scan_info(w.Q, args.k)[0]
-    scan_bytes = w.N * plane_bytes * passes + w.Q * row_bytes
+    groups = idx.scan_info(w.Q, args.k)[0]
+    scan_bytes = w.N * plane_bytes + w.Q * row_bytes
 
     # ---- serving at fixed offered load (Poisson arrivals, batches of 1-256 queries)
     serving = None
@@ -430,6 +434,9 @@ def main():
             cl.replay(events=e)
         torch.cuda.synchronize()
         staged_dev = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        # the same replay timed like the per-bucket launches: back-to-back on
+        # one stream between two events
+        staged_b2b = device_ms(lambda: cl.replay(), cur)
         staged_same = bool(torch.equal(cl.ids[:int(ku.sum())], ref.ids) and torch.equal(cl.lcps[:int(ku.sum())], ref.lcps))
         # every shape the autotuner tried, and the per-bucket launches, against the C oracle on all queries
         shapes_exact = None
@@ -466,6 +473,8 @@ def main():
                   "per_k_bucket_launches_gpu_ms": round(per_bucket_dev, 4),
                   "captured_ms": round(captured, 4), "captured_gpu_ms": round(captured_dev, 4),
                   "captured_staged_replay_gpu_ms": round(staged_dev, 4),
+                  "back_to_back_gpu_ms": {"per_k_bucket_launches": round(per_bucket_dev, 4),
+                                          "captured_staged_replay": round(staged_b2b, 4)},
                   "captured_staged_replay_equals_plain": staged_same,
                   "oracle_exact_by_shape": shapes_exact,
                   "captured_shape": (tune["best"].mode, tune["best"].blocks),
@@ -603,11 +612,13 @@ def main():
         "work_shape": shape,
         "scan": {"qps": round(scan_qps, 1), "ms_per_batch": round(sdt * 1e3 / args.scan_steps, 4),
                  "index_speedup": round(qps / scan_qps, 2), "scan_kernel_ms": round(scan_kernel_ms, 4),
-                 "merge_kernel_ms": round(m_ms / max(m_n, 1), 4), "passes_over_db": passes,
-                 "plane_GBps": round(scan_bytes / (scan_kernel_ms * 1e-3) / 1e9, 1),
+                 "merge_kernel_ms": round(m_ms / max(m_n, 1), 4), "query_groups": groups,
+                 "hbm_GBps": round(scan_bytes / (scan_kernel_ms * 1e-3) / 1e9, 1),
+                 "l2_stream_GBps": round((w.N * plane_bytes * groups + w.Q * row_bytes) / (scan_kernel_ms * 1e-3) / 1e9, 1),
                  "pair_lcp_per_s": round(w.Q * w.N / (scan_kernel_ms * 1e-3), 1),
                  "paths_bit_identical": paths_agree},
-        "scan_roofline": {"kernel": "k_scan", "bound": "hbm", "queries": nbw, "passes_over_db": passes_bw,
+        "scan_roofline": {"kernel": "k_scan", "bound": "hbm", "queries": nbw, "query_groups": groups_bw,
+                          "bytes_per_launch": int(bw_bytes),
                           "achieved": round(bw_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(bw_gbs / HBM_PEAK_GBS, 4),
                           "avg_kernel_us": round(bw_ms / bw_n * 1e3, 2),

@@ -60,7 +60,14 @@ __device__ __forceinline__ void limit_filter(uint64_t lim, int64_t next_id, uint
 // so the answer's k'-th key is below rank_key(t, S): every answer row beats
 // that key, which becomes the query's limit.  Block b counts part b % parts
 // of the sample for query b / parts.
+//
+// The 8-byte plane decides every LCP below cmax, the tokens it holds: each
+// wave counts its rows with LCP >= d for d = 1..cmax with one ballot per level
+// (no per-row histogram updates), and only rows that agree with the query on
+// all cmax tokens read the rest of the row and add to the histogram one by one.
 constexpr int kSeedThreads = 256;
+constexpr int kSeedU = 8;
+constexpr int kSeedLevels = 8;  // cmax <= 8 (eight 1-byte tokens in the plane)
 __global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const uint32_t* __restrict__ qkeys,
                                                             int64_t S, int parts, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];                 // LCP 0..L, L <= 255
@@ -75,40 +82,55 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const 
     const int64_t per = (S + parts - 1) / parts;
     const int64_t r0 = (int64_t)part * per;
     const int64_t r1 = r0 + per < S ? r0 + per : S;
-    for (int64_t base = r0; base < r1; base += kSeedThreads) {
-        const int64_t r = base + threadIdx.x;
-        const bool act = r < r1;
-        int lc = g.L;
-        if (act) {
-            const uint64_t pw = ix.plane[r];
-            const uint32_t x0 = (uint32_t)(pw >> 32) ^ qw[0];
-            const uint32_t x1 = g.W > 1 ? (uint32_t)pw ^ qw[1] : 0u;
-            if (x0) {
-                lc = lcp_from_diff(0, x0, g);
-            } else if (x1) {
-                lc = lcp_from_diff(1, x1, g);
-            } else {
+    const int plane_tokens = (g.W > 1 ? 8 : 4) / g.tb;
+    const int cmax = g.L < plane_tokens ? g.L : plane_tokens;
+    const uint32_t q0 = qw[0], q1 = g.W > 1 ? qw[1] : 0u;
+    uint32_t rows = 0;
+    uint32_t ge[kSeedLevels];  // ge[d - 1]: this wave's rows with LCP >= d (wave-uniform)
+#pragma unroll
+    for (int d = 0; d < kSeedLevels; ++d) ge[d] = 0;
+    // kSeedU rows per thread and round, all loads in flight before any is used
+    for (int64_t base = r0; base < r1; base += (int64_t)kSeedThreads * kSeedU) {
+        uint64_t pw[kSeedU];
+#pragma unroll
+        for (int u = 0; u < kSeedU; ++u) {
+            const int64_t r = base + u * kSeedThreads + threadIdx.x;
+            pw[u] = r < r1 ? ix.plane[r] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kSeedU; ++u) {
+            const int64_t r = base + u * kSeedThreads + threadIdx.x;
+            const bool act = r < r1;
+            const uint32_t x0 = (uint32_t)(pw[u] >> 32) ^ q0, x1 = (uint32_t)pw[u] ^ q1;
+            const int lc = x0 ? lcp_from_diff(0, x0, g) : x1 ? lcp_from_diff(1, x1, g) : cmax;
+            rows += (uint32_t)popc64(ballot(act));
+#pragma unroll
+            for (int d = 1; d <= kSeedLevels; ++d)
+                if (d <= cmax) ge[d - 1] += (uint32_t)popc64(ballot(act && lc >= d));
+            if (act && lc == cmax && g.L > cmax) {  // the rest of the row decides
                 const uint32_t* row = ix.rows + r * g.W;
+                int full = g.L;
                 for (int w = 2; w < g.W; ++w) {
                     const uint32_t x = row[w] ^ qw[w];
                     if (x) {
-                        lc = lcp_from_diff(w, x, g);
+                        full = lcp_from_diff(w, x, g);
                         break;
                     }
                 }
+                atomicAdd(&h[full], 1u);
             }
         }
-        // rows sharing no token with the query (most of them) in one add,
-        // then one LDS add per distinct nonzero LCP value in the wave
-        const uint64_t zero = ballot(act && lc == 0);
-        if (lane == 0 && zero) atomicAdd(&h[0], (uint32_t)popc64(zero));
-        uint64_t pending = ballot(act && lc != 0);
-        while (pending) {
-            const int v = readlane_i(lc, low_lane(pending));
-            const uint64_t same = ballot(((pending >> lane) & 1ull) && lc == v);
-            if (lane == low_lane(same)) atomicAdd(&h[v], (uint32_t)popc64(same));
-            pending &= ~same;
+    }
+    // exact counts below cmax from the level counts; at cmax itself only when
+    // the plane holds the whole row
+    if (lane == 0) {
+        uint32_t above = rows;
+        for (int d = 1; d <= cmax; ++d) {
+            const uint32_t cur = ge[d - 1];
+            if (above - cur) atomicAdd(&h[d - 1], above - cur);
+            above = cur;
         }
+        if (g.L == cmax && above) atomicAdd(&h[cmax], above);
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= g.L; i += kSeedThreads)
@@ -194,9 +216,10 @@ struct ScanGrid {
 //    reach later) into one of two small hash tables in LDS, one per mask
 //    length, keyed by the masked query value; per row and table the hot loop
 //    costs one hash, one LDS read and two 64-bit compares however many
-//    queries the table holds, and a step with a hit tests its queries one by
-//    one.  Queries that do not fit (a third mask length, a full slot, no
-//    limit) are tested one by one on every step;
+//    queries the table holds; each slot also holds the set of queries whose
+//    keys fall in it, and a step with a hit tests the queries of the matched
+//    slots one by one.  Queries that do not fit (a third mask length, a full
+//    slot, no limit) are tested one by one on every step;
 //  - one by one: the query's current filter (lane i holds query i's) against
 //    the step's rows, one 64-bit compare per row, and two ANDs when the
 //    filter keeps part of the 64 bits.
@@ -209,6 +232,7 @@ struct ScanGrid {
 // part + q * cap, fill count in cnt[q]); the append order does not matter,
 // the merge ranks by key.
 constexpr int kScanU = 4;                                  // 16-byte loads per lane per step
+constexpr int kQwRegs = 4;                                 // query words per thread fetched with the first loads
 constexpr int64_t kPairRows = 2 * kWave;                   // rows of one 16-byte load of the wave
 constexpr int64_t kScanStepRows = kScanU * kPairRows;      // rows per wave step
 constexpr int kGthrEvery = 4;                              // steps between pick-ups of shared limits
@@ -218,22 +242,25 @@ constexpr uint64_t kHashEmpty = ~0ull;                     // an empty slot's ke
 
 // Block-shared pre-filter state in LDS.
 struct ScanHash {
-    uint4 slot[kHashTables][kHashSlots];  // (key0 lo, key0 hi, key1 lo, key1 hi)
-    uint32_t fill[kHashTables][kHashSlots];
+    uint4 slot[kHashTables][kHashSlots];     // (key0 lo, key0 hi, key1 lo, key1 hi)
+    uint64_t qbits[kHashTables][kHashSlots];  // the queries whose key falls in the slot
     uint64_t mask[kHashTables];
     uint64_t left;  // queries tested one by one on every step
     int32_t ntab;
     int32_t pad_;
 };
 
+// Shifts and XORs only (full-rate VALU operations; a 32-bit multiply issues
+// at a quarter of the rate).
 __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
-    const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
-    const uint32_t x = hi ^ lo ^ (hi >> 16);
-    return (__umul24(x & 0xFFFFFFu, 0x9E3779u) >> 13) & (kHashSlots - 1);
+    uint32_t x = (uint32_t)(key >> 32) ^ (uint32_t)key;
+    x ^= x >> 16;
+    x ^= x >> 7;
+    return x & (kHashSlots - 1);
 }
 
 template <int NR, int TQ, bool kHash>
-__global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, QueryBatch qb,
+__global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 6 : 1))) void k_scan(IndexView ix, QueryBatch qb,
                                                              const uint32_t* __restrict__ qkeys, ScanGrid sg,
                                                              int64_t cap, uint64_t* __restrict__ part,
                                                              uint32_t* __restrict__ cnt,
@@ -262,6 +289,47 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                                    : sg.seed_rows + (int64_t)(pi - sg.seed_chunks) * sg.chunk_rows;
     };
 
+    // the wave's rows [r_lo, r_hi) as pairs [p_lo, p_last]: r_lo is even, and
+    // an odd N has a zero entry after its last row; loads past the chunk
+    // re-read its last pair.  The first step's loads go out before any of the
+    // set-up below (waves past the last chunk only help set up the block).
+    // everything the set-up reads from memory is requested first, in one
+    // round trip with the first plane loads: the group's query words (up to
+    // kQwRegs per thread here, the rest below), and lane i's query limit and k
+    const int nqw = ntq * W;
+    uint32_t qwr[kQwRegs];
+#pragma unroll
+    for (int j = 0; j < kQwRegs; ++j) {
+        const int t = j * kScanWaves * kWave + (int)threadIdx.x;
+        qwr[j] = t < nqw ? qkeys[q0i * W + t] : 0u;
+    }
+    const bool lane_real = lane < ntq;
+    const uint64_t lim0 = lane_real ? gthr[q0i + lane] : kKeyMax;
+    const int k0 = lane_real ? query_k(qb, q0i + lane) : 1;
+
+    const bool active = pidx < sg.nparts;
+    int64_t r_lo = 0, r_hi = 0;
+    if (active) {
+        r_lo = chunk_lo(pidx);
+        if (pidx < sg.seed_chunks)
+            r_hi = r_lo + sg.seed_chunk_rows < sg.seed_rows ? r_lo + sg.seed_chunk_rows : sg.seed_rows;
+        else
+            r_hi = r_lo + sg.chunk_rows < N ? r_lo + sg.chunk_rows : N;
+    }
+    const uint4* __restrict__ pl = reinterpret_cast<const uint4*>(ix.plane);
+    const int64_t p_lo = r_lo >> 1, p_last = ((r_hi + 1) >> 1) - 1;
+    uint4 nx[kScanU];
+    if (active) {
+#pragma unroll
+        for (int u = 0; u < kScanU; ++u) {
+            const int64_t pp = p_lo + u * kWave + lane;
+            nx[u] = pl[pp < p_last ? pp : p_last];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kScanU; ++u) nx[u] = make_uint4(0u, 0u, 0u, 0u);
+    }
+
     // LDS: [TQ][W] query words, the pre-filter (hashed variants), then per
     // wave [TQ] filters and [TQ][lstride] list entries
     uint32_t* s_q = reinterpret_cast<uint32_t*>(s_dyn64);
@@ -271,12 +339,17 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     ScanFilter* filt = reinterpret_cast<ScanFilter*>(s_dyn64 + qwords64 + hash64) + wv * TQ;
     uint64_t* lists = s_dyn64 + qwords64 + hash64 + (size_t)kScanWaves * TQ * (sizeof(ScanFilter) / 8) +
                       (size_t)wv * TQ * sg.lstride;
-    for (int t = threadIdx.x; t < TQ * W; t += kScanWaves * kWave)
-        s_q[t] = t < ntq * W ? qkeys[q0i * W + t] : 0u;
+#pragma unroll
+    for (int j = 0; j < kQwRegs; ++j) {
+        const int t = j * kScanWaves * kWave + (int)threadIdx.x;
+        if (t < TQ * W) s_q[t] = qwr[j];
+    }
+    for (int t = kQwRegs * kScanWaves * kWave + (int)threadIdx.x; t < TQ * W; t += kScanWaves * kWave)
+        s_q[t] = t < nqw ? qkeys[q0i * W + t] : 0u;
     if constexpr (kHash) {
         for (int t = threadIdx.x; t < kHashTables * kHashSlots; t += kScanWaves * kWave) {
             (&hs->slot[0][0])[t] = make_uint4(~0u, ~0u, ~0u, ~0u);
-            (&hs->fill[0][0])[t] = 0u;
+            (&hs->qbits[0][0])[t] = 0ull;
         }
     }
     __syncthreads();
@@ -288,7 +361,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
             if (lane < ntq) {
                 const uint32_t* q = s_q + lane * W;
                 const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
-                limit_filter(gthr[q0i + lane], chunk_lo(pidx0), q01, g, msk, qm);
+                limit_filter(lim0, chunk_lo(pidx0), q01, g, msk, qm);
             }
             // up to two mask lengths get a table; a query without a limit
             // (mask 0) or with another mask length is tested one by one
@@ -308,11 +381,13 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                     ntab = 2;
                 }
             }
-            // claim a place in the slot: the first key of a slot also fills
-            // its second place, a second key then overwrites that place
+            // join the slot's query set; the queries already in it give the
+            // place: the first key of a slot also fills its second place, a
+            // second key then overwrites that place, later ones go one by one
             uint32_t sl = tab >= 0 ? hash_slot(qm) : 0u;
             uint32_t pos = 2;
-            if (tab >= 0) pos = atomicAdd(&hs->fill[tab][sl], 1u);
+            if (tab >= 0)
+                pos = (uint32_t)popc64(atomicOr((unsigned long long*)&hs->qbits[tab][sl], 1ull << lane));
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -335,31 +410,15 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         }
         __syncthreads();
     }
-    if (pidx >= sg.nparts) return;
+    if (!active) return;
 
-    int64_t r_lo = chunk_lo(pidx), r_hi;
-    if (pidx < sg.seed_chunks)
-        r_hi = r_lo + sg.seed_chunk_rows < sg.seed_rows ? r_lo + sg.seed_chunk_rows : sg.seed_rows;
-    else
-        r_hi = r_lo + sg.chunk_rows < N ? r_lo + sg.chunk_rows : N;
-    // pairs of rows [p_lo, p_hi): r_lo is even, and an odd N has a zero entry
-    // after its last row; loads past the chunk re-read its last pair.  The
-    // first step's loads go out before the filters are set up.
-    const uint4* __restrict__ pl = reinterpret_cast<const uint4*>(ix.plane);
-    const int64_t p_lo = r_lo >> 1, p_last = ((r_hi + 1) >> 1) - 1;
-    uint4 nx[kScanU];
-#pragma unroll
-    for (int u = 0; u < kScanU; ++u) {
-        const int64_t pp = p_lo + u * kWave + lane;
-        nx[u] = pl[pp < p_last ? pp : p_last];
-    }
     // the wave's filters from the starting limits; query slots past the batch
     // get one that nothing matches
     if (lane < TQ) {
         ScanFilter f;
         const bool is_real = lane < ntq;
-        f.lim = is_real ? gthr[q0i + lane] : kKeyMax;
-        const int ki = is_real ? query_k(qb, q0i + lane) : 1;
+        f.lim = lim0;
+        const int ki = k0;
         f.kk = (int)((int64_t)ki < N ? (int64_t)ki : N);
         f.pad_ = 0;
         const uint32_t* q = s_q + lane * W;
@@ -447,20 +506,47 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
         // slow path drops them.
         uint64_t test = one_by_one;
         if constexpr (kHash) {
-            uint64_t hit = 0;
+            uint64_t hitq = 0;
 #pragma unroll 1
             for (int t0 = 0; t0 < ntab; ++t0) {
                 const uint64_t m = hmask[t0];
                 const uint4* tab = hs->slot[t0];
+                uint64_t hit = 0;
+                if (m == ~0ull) {
 #pragma unroll
-                for (int t = 0; t < 2 * kScanU; ++t) {
-                    const uint64_t key = m == ~0ull ? v[t] : v[t] & m;
-                    const uint4 e = tab[hash_slot(key)];
-                    const uint64_t k0 = ((uint64_t)e.y << 32) | e.x, k1 = ((uint64_t)e.w << 32) | e.z;
-                    hit |= ballot(key == k0 || key == k1);
+                    for (int t = 0; t < 2 * kScanU; ++t) {
+                        const uint4 e = tab[hash_slot(v[t])];
+                        hit |= ballot(v[t] == (((uint64_t)e.y << 32) | e.x));
+                        hit |= ballot(v[t] == (((uint64_t)e.w << 32) | e.z));
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 2 * kScanU; ++t) {
+                        const uint64_t key = v[t] & m;
+                        const uint4 e = tab[hash_slot(key)];
+                        hit |= ballot(key == (((uint64_t)e.y << 32) | e.x));
+                        hit |= ballot(key == (((uint64_t)e.w << 32) | e.z));
+                    }
+                }
+                if (hit) {
+                    // rare: collect the query sets of the matched slots, so
+                    // that only those queries are tested one by one
+#pragma unroll 1
+                    for (int t = 0; t < 2 * kScanU; ++t) {
+                        uint64_t w = v[0];
+#pragma unroll
+                        for (int tt = 1; tt < 2 * kScanU; ++tt) w = t == tt ? v[tt] : w;
+                        const uint64_t key = w & m;
+                        const uint32_t sl = hash_slot(key);
+                        const uint4 e = tab[sl];
+                        const uint64_t k0 = ((uint64_t)e.y << 32) | e.x, k1 = ((uint64_t)e.w << 32) | e.z;
+                        const bool match = key == k0 || key == k1;
+                        const uint64_t qs = match ? hs->qbits[t0][sl] : 0ull;
+                        for (uint64_t mm = ballot(match); mm; mm &= mm - 1) hitq |= readlane64(qs, low_lane(mm));
+                    }
                 }
             }
-            if (hit) test |= hashed;
+            test |= hitq & hashed;
         }
         uint64_t flagged = 0;
 #pragma unroll 1
@@ -477,8 +563,34 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
             }
             flagged |= any ? (1ull << i) : 0ull;
         }
-        // slow path, one flagged query at a time, its rows in id order
+        // slow path, one flagged query at a time, its rows in id order.  A row
+        // that agrees with the query on the whole plane needs the row's next
+        // words: each lane fetches words 2-3 of its first such row (for any
+        // flagged query) once for the step, so that one round trip serves
+        // them all; a lane's further such rows read theirs on their own.
         const bool any_flagged = flagged != 0;
+        int tail_t = -1;
+        uint32_t tw2 = 0, tw3 = 0;
+        if (any_flagged && W > 2) {
+#pragma unroll 1
+            for (uint64_t todo = flagged; todo; todo &= todo - 1) {
+                const uint32_t* q = s_q + low_lane(todo) * W;
+                const uint64_t q01 = ((uint64_t)q[0] << 32) | q[1];
+#pragma unroll
+                for (int t = 2 * kScanU - 1; t >= 0; --t)
+                    if (v[t] == q01) tail_t = t < tail_t || tail_t < 0 ? t : tail_t;
+            }
+            if (tail_t >= 0) {
+                const int64_t id = base + (tail_t >> 1) * kPairRows + 2 * lane + (tail_t & 1);
+                if (id < r_hi) {
+                    const uint32_t* rp = ix.rows + id * W;
+                    tw2 = rp[2];
+                    tw3 = W > 3 ? rp[3] : 0u;
+                } else {
+                    tail_t = -1;
+                }
+            }
+        }
 #pragma unroll 1
         while (flagged) {
             const int i = low_lane(flagged);
@@ -511,16 +623,23 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
                         lc = lcp_from_diff(0, (uint32_t)(x >> 32), g);
                     else if ((uint32_t)x)
                         lc = lcp_from_diff(1, (uint32_t)x, g);
+                    else if (W <= 2)
+                        lc = g.L;
+                    else if (t != tail_t)
+                        lc = lcp_tail(ix.rows + id * W, q, g, 2);
+                    else if (tw2 ^ q[2])
+                        lc = lcp_from_diff(2, tw2 ^ q[2], g);
+                    else if (W == 3)
+                        lc = g.L;
+                    else if (tw3 ^ q[3])
+                        lc = lcp_from_diff(3, tw3 ^ q[3], g);
                     else
-                        lc = W > 2 ? lcp_tail(ix.rows + id * W, q, g, 2) : g.L;
+                        lc = W > 4 ? lcp_tail(ix.rows + id * W, q, g, 4) : g.L;
                 }
                 const uint64_t key = rank_key(lc, (uint32_t)id);
                 lst.offer(key, cand && key < f.lim, f.kk);
                 const uint64_t kth = lst.get(f.kk - 1);
-                if (kth < f.lim) {
-                    f.lim = kth;
-                    if (lane == 0) atomicMin((unsigned long long*)(gthr + q0i + i), (unsigned long long)kth);
-                }
+                if (kth < f.lim) f.lim = kth;
                 // rows still to come: the second row of this pair, or the next pairs
                 limit_filter(f.lim, base + u * kPairRows + (h == 0 ? 1 : kPairRows), q01, g, f.msk, f.qm);
             }
@@ -542,29 +661,32 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_scan(IndexView ix, Query
     // entries above a valid limit cannot be in the answer; each list is
     // ascending, so the kept ones are a prefix.  The wave's own limit is used
     // (the shared one may be tighter, but reading it would cost another round
-    // trip; the merge ranks whatever is kept).  Lane i counts query i's and
+    // trip; the merge ranks whatever is kept).  Lane i counts query i's (most
+    // lists are empty: the count stops at the first entry not kept) and
     // reserves room for them with one atomic for all the wave's queries.
     int mine = 0;
-#pragma unroll 1
-    for (int i = 0; i < ntq; ++i) {
-        const int kk = filt[i].kk;
-        const uint64_t keep = filt[i].lim;
-        const uint64_t* lp = lists + (size_t)i * sg.lstride;
-        int n = 0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int e = r * kWave + lane;
-            const uint64_t x = e < kk ? lp[e] : kKeyMax;
-            n += popc64(ballot(x != kKeyMax && x <= keep));
+    if (lane < ntq) {
+        const int kk = filt[lane].kk;
+        const uint64_t keep = filt[lane].lim;
+        const uint64_t* lp = lists + (size_t)lane * sg.lstride;
+        for (int e = 0; e < kk; ++e) {
+            const uint64_t x = lp[e];
+            if (x == kKeyMax || x > keep) break;
+            ++mine;
         }
-        mine = lane == i ? n : mine;
+    }
+    // limits this wave tightened go to the shared ones once, here (waves that
+    // start later read them)
+    if (lane < ntq) {
+        const uint64_t mylim = filt[lane].lim;
+        if (mylim < lim0) atomicMin((unsigned long long*)(gthr + q0i + lane), (unsigned long long)mylim);
     }
     uint32_t at = 0;
     if (lane < ntq && mine > 0) at = atomicAdd(cnt + (q0i + lane) * kCntStride, (uint32_t)mine);
 #pragma unroll 1
-    for (int i = 0; i < ntq; ++i) {
+    for (uint64_t todo = ballot(mine > 0); todo; todo &= todo - 1) {
+        const int i = low_lane(todo);
         const int n = readlane_i(mine, i);
-        if (n == 0) continue;
         uint64_t* dst = part + (q0i + i) * cap + (uint32_t)readlane_i((int)at, i);
         const uint64_t* lp = lists + (size_t)i * sg.lstride;
         for (int e = lane; e < n; e += kWave) dst[e] = lp[e];
@@ -697,27 +819,28 @@ constexpr size_t kScanLdsBudget = 40 << 10;  // per block: at least 4 blocks (16
 // size, about kHashCost compares (measured on the 2M- and 8M-row hierarchy
 // databases: its random LDS reads and its registers, 108 against 75, make the
 // hashed variant slower at 32 queries and faster from a few hundred on).
-constexpr int kHashCost = 48;
+constexpr int kHashCost = 12;
 struct ScanShape {
     int tq;
     bool hash;
 };
 static ScanShape shape_for(int nr, int32_t k_max, int64_t Q, int W) {
-    static const ScanShape c1[] = {{64, true}, {16, false}, {8, false}, {2, false}, {1, false}},
+    static const ScanShape c1[] = {{64, true}, {32, true}, {16, false}, {8, false}, {2, false}, {1, false}},
                            c2[] = {{16, true}, {8, false}, {1, false}}, c4[] = {{4, false}, {1, false}},
                            c16[] = {{1, false}};
     const ScanShape* c = nr == 1 ? c1 : nr == 2 ? c2 : nr == 4 ? c4 : c16;
-    const int n = nr == 1 ? 5 : nr == 2 ? 3 : nr == 4 ? 2 : 1;
+    const int n = nr == 1 ? 6 : nr == 2 ? 3 : nr == 4 ? 2 : 1;
     ScanShape best = {1, false};
-    int64_t best_cost = Q;
-    for (int i = n - 1; i >= 0; --i) {  // ascending tq: a larger one wins ties
+    int64_t best_cost = Q, best_groups = Q;
+    for (int i = n - 1; i >= 0; --i) {  // ascending tq: on equal cost a larger one wins only with fewer groups
         const ScanShape sh = c[i];
         if (sh.tq > 1 && scan_block_lds(sh.tq, sh.hash, k_max, W) > kScanLdsBudget) continue;
         const int64_t groups = (Q + sh.tq - 1) / sh.tq;
         const int64_t cost = groups * (sh.hash ? kHashCost : (Q < sh.tq ? Q : sh.tq));
-        if (cost <= best_cost) {
+        if (cost < best_cost || (cost == best_cost && groups < best_groups)) {
             best = sh;
             best_cost = cost;
+            best_groups = groups;
         }
     }
     return best;
@@ -727,6 +850,7 @@ static ScanShape shape_for(int nr, int32_t k_max, int64_t Q, int W) {
 constexpr int64_t kChunkMinRows = 2 * kScanStepRows;
 constexpr int64_t kSeedRows = 65536;
 constexpr int64_t kScanTargetWaves = 8192;  // 32 per CU
+constexpr int64_t kChunkAlign = kScanStepRows;  // main chunks: whole steps
 
 ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budget_bytes) {
     ScanPlan p;
@@ -783,7 +907,7 @@ ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budg
         if (chunks > max_by_mem - p.seed_chunks) chunks = max_by_mem - p.seed_chunks;
         if (chunks < 1) chunks = 1;
         int64_t rows = (rest + chunks - 1) / chunks;
-        rows = (rows + kScanStepRows - 1) / kScanStepRows * kScanStepRows;
+        rows = (rows + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
         p.chunk_rows = rows;
         p.chunks = (int)((rest + rows - 1) / rows);
     }
@@ -840,6 +964,7 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
     if (ev0) hipEventRecord(ev0, s);
     switch (p.nr * 1000 + p.tq * 10 + (p.hash ? 1 : 0)) {
         case 1641: launch_scan_t<1, 64, true>(ix, qb, p, sc, qb.k_max, s); break;
+        case 1321: launch_scan_t<1, 32, true>(ix, qb, p, sc, qb.k_max, s); break;
         case 1160: launch_scan_t<1, 16, false>(ix, qb, p, sc, qb.k_max, s); break;
         case 1080: launch_scan_t<1, 8, false>(ix, qb, p, sc, qb.k_max, s); break;
         case 1020: launch_scan_t<1, 2, false>(ix, qb, p, sc, qb.k_max, s); break;

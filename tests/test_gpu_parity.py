@@ -697,3 +697,23 @@ def test_append_rows_equal_in_their_first_bytes(P, L, V):
     for key in ("perm", "adj_lcp", "sorted_keys", "id_keys"):
         assert (va[key] == vb[key]).all(), key
     assert (va["perm"] == O.sorted_permutation(whole)).all()
+
+
+@pytest.mark.parametrize("k", [1, 10, 64, 65, 200, 300])
+def test_scan_every_launch_shape(P, k):
+    """The full scan splits a batch into query groups whose size and test
+    (one query at a time, or the hashed pre-filter) depend on the batch size
+    and k: batch sizes around each group-size boundary cover every compiled
+    shape, each against the C oracle, bit-exact."""
+    w = synth.c3_like(200_000, 256, seed=1031, k_fixed=k)
+    seen = set()
+    with P.Index(w.db, w.V) as idx:
+        for Q in (1, 2, 5, 8, 12, 13, 16, 17, 32, 33, 64, 65, 200):
+            qs = w.queries[:Q]
+            seen.add(idx.scan_info(Q, k)[0] / Q)
+            b = idx.scan_topk(qs, k)
+            gi, gl = b.ids.cpu().numpy(), b.lcps.cpu().numpy()
+            wi, wl, woff = oracle.c_topk(w.db, qs, k)
+            _assert_equal(gi, gl, wi, wl, woff, f"scan Q={Q} k={k}")
+    # shapes compiled per list size: k <= 64 six, k <= 128 three, k <= 256 two, above one
+    assert len(seen) >= (4 if k <= 64 else 2 if k <= 256 else 1), seen
