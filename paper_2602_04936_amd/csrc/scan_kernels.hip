@@ -54,12 +54,15 @@ __device__ __forceinline__ void limit_filter(uint64_t lim, int64_t next_id, uint
 }
 
 
-// Starting limits from the first S rows (ids 0..S-1).  hist[q][d] counts the
-// sample rows with LCP exactly d.  With t the largest d such that at least k'
-// sample rows have LCP >= d, those k' rows have keys <= rank_key(t, S - 1),
-// so the answer's k'-th key is below rank_key(t, S): every answer row beats
-// that key, which becomes the query's limit.  Block b counts part b % parts
-// of the sample for query b / parts.
+// Starting limits from the first S rows (ids 0..S-1), cut into `parts`
+// consecutive id ranges.  hist[q][p][d] counts the rows of part p with LCP
+// exactly d.  With t the largest d such that at least k' sample rows have
+// LCP >= d, and p* the first part at whose end the sample rows with LCP > t
+// plus those of parts 0..p* with LCP == t number at least k', those k' rows
+// have keys <= rank_key(t, X - 1), X the end of part p*: the answer's k'-th
+// key is below rank_key(t, X), every answer row beats that key, and it
+// becomes the query's limit (rows with LCP == t after X need not be looked
+// at).  Block b counts part b % parts of the sample for query b / parts.
 //
 // The 8-byte plane decides every LCP below cmax, the tokens it holds: each
 // wave counts its rows with LCP >= d for d = 1..cmax with one ballot per level
@@ -133,32 +136,43 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_hist(IndexView ix, const 
         if (g.L == cmax && above) atomicAdd(&h[cmax], above);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i <= g.L; i += kSeedThreads)
-        if (h[i]) atomicAdd(hist + qi * (g.L + 1) + i, h[i]);
+    uint32_t* hq = hist + ((size_t)qi * parts + part) * (g.L + 1);  // this block's own histogram
+    for (int i = threadIdx.x; i <= g.L; i += kSeedThreads) hq[i] = h[i];
 }
 
-// One wave per query.  Lane i takes d = top - i, so the wave's inclusive
-// prefix sum at lane i counts the sample rows with LCP in [d, top] (plus the
-// rows above top from earlier passes); the first lane where it reaches k'
-// gives the largest d with at least k' sample rows of LCP >= d.  All of a
-// pass's histogram loads are in flight at once.
+// One wave per query.  Lane i takes d = top - i and sums that level over the
+// parts, so the wave's inclusive prefix sum at lane i counts the sample rows
+// with LCP in [d, top] (plus the rows above top from earlier passes); the
+// first lane where it reaches k' gives t.  Then lane p takes part p's rows at
+// LCP t, and the first lane where the rows above t plus the prefix sum reach
+// k' gives p*.
 __global__ __launch_bounds__(kScanWaves * kWave) void k_seed_limit(QueryBatch qb, int64_t N, int L, int64_t S,
-                                                                   const uint32_t* __restrict__ hist,
+                                                                   int parts, const uint32_t* __restrict__ hist,
                                                                    uint64_t* __restrict__ gthr) {
     const int lane = lane_id();
     const int64_t qi = (int64_t)blockIdx.x * kScanWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (qi >= qb.Q) return;
     const int k = query_k(qb, qi);
     const uint32_t kk = (uint32_t)((int64_t)k < N ? (int64_t)k : N);
-    const uint32_t* h = hist + qi * (L + 1);
+    const uint32_t* h = hist + qi * (int64_t)parts * (L + 1);
     uint64_t lim = kKeyMax;
     uint32_t above = 0;  // sample rows with LCP above this pass's top
     for (int top = L; top >= 0; top -= kWave) {
         const int d = top - lane;
-        const uint32_t acc = wave_prefix_sum(d >= 0 ? h[d] : 0u) + above;
+        uint32_t c = 0;
+        if (d >= 0)
+            for (int p = 0; p < parts; ++p) c += h[(int64_t)p * (L + 1) + d];
+        const uint32_t acc = wave_prefix_sum(c) + above;
         const uint64_t ok = ballot(d >= 0 && acc >= kk);
         if (ok) {
-            lim = rank_key(top - low_lane(ok), (uint32_t)S);
+            const int i = low_lane(ok);
+            const int t = top - i;
+            const uint32_t gt = readlane(acc, i) - readlane(c, i);  // sample rows with LCP > t
+            const uint32_t ct = lane < parts ? h[(int64_t)lane * (L + 1) + t] : 0u;
+            const uint64_t reach = ballot(lane < parts && wave_prefix_sum(ct) + gt >= kk);
+            const int64_t per = (S + parts - 1) / parts;
+            const int64_t end = (int64_t)(low_lane(reach) + 1) * per;
+            lim = rank_key(t, (uint32_t)(end < S ? end : S));
             break;
         }
         above = readlane(acc, kWave - 1);
@@ -171,9 +185,9 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_seed_limit(QueryBatch qb
 // k-th best of k real rows), so every wave may skip such rows.  The limit
 // only prunes; the merged answer is the unique exact top-k either way.
 
-// One launch before the scan: zero the fill counts and histograms (a kernel,
-// not a memset, so the sequence can be captured in a graph) and compute the
-// query key words once for every block to copy.
+// One launch before the scan: zero the fill counts (a kernel, not a memset,
+// so the sequence can be captured in a graph) and compute the query key words
+// once for every block to copy.
 __global__ void k_scan_prep(QueryBatch qb, RowGeo g, uint32_t* __restrict__ zero, int64_t nz,
                             uint32_t* __restrict__ qkeys) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -284,15 +298,20 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
     const uint64_t real = ntq >= 64 ? ~0ull : (1ull << ntq) - 1;
     const int64_t N = ix.N;
 
-    auto chunk_lo = [&](int pi) -> int64_t {
-        return pi < sg.seed_chunks ? (int64_t)pi * sg.seed_chunk_rows
-                                   : sg.seed_rows + (int64_t)(pi - sg.seed_chunks) * sg.chunk_rows;
+    // rows of part p: the seed chunks first (sampled rows: their looser
+    // filters leave them most of the slow-path work, and in the first blocks
+    // dispatched that work overlaps the rest of the pass instead of trailing
+    // it), then the main chunks
+    auto chunk_rows_of = [&](int p, int64_t& lo, int64_t& hi) {
+        if (p < sg.seed_chunks) {
+            lo = (int64_t)p * sg.seed_chunk_rows;
+            hi = lo + sg.seed_chunk_rows < sg.seed_rows ? lo + sg.seed_chunk_rows : sg.seed_rows;
+        } else {
+            lo = sg.seed_rows + (int64_t)(p - sg.seed_chunks) * sg.chunk_rows;
+            hi = lo + sg.chunk_rows < N ? lo + sg.chunk_rows : N;
+        }
     };
 
-    // the wave's rows [r_lo, r_hi) as pairs [p_lo, p_last]: r_lo is even, and
-    // an odd N has a zero entry after its last row; loads past the chunk
-    // re-read its last pair.  The first step's loads go out before any of the
-    // set-up below (waves past the last chunk only help set up the block).
     // everything the set-up reads from memory is requested first, in one
     // round trip with the first plane loads: the group's query words (up to
     // kQwRegs per thread here, the rest below), and lane i's query limit and k
@@ -303,32 +322,31 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
         const int t = j * kScanWaves * kWave + (int)threadIdx.x;
         qwr[j] = t < nqw ? qkeys[q0i * W + t] : 0u;
     }
+    // (clamped indices instead of masked loads: no branch, so nothing waits
+    // for these before the plane loads go out)
     const bool lane_real = lane < ntq;
-    const uint64_t lim0 = lane_real ? gthr[q0i + lane] : kKeyMax;
-    const int k0 = lane_real ? query_k(qb, q0i + lane) : 1;
+    const int lq_idx = lane_real ? lane : 0;
+    const uint64_t lim_ld = gthr[q0i + lq_idx];
+    int k_ld = qb.k_uniform;
+    if (qb.k_uniform <= 0) k_ld = qb.k[q0i + lq_idx];
 
+    // the wave's rows [r_lo, r_hi) as pairs [p_lo, p_last]: r_lo is even, and
+    // an odd N has a zero entry after its last row; loads past the chunk
+    // re-read its last pair.  The first step's loads go out before any of the
+    // set-up below (waves past the last chunk only help set up the block).
     const bool active = pidx < sg.nparts;
-    int64_t r_lo = 0, r_hi = 0;
-    if (active) {
-        r_lo = chunk_lo(pidx);
-        if (pidx < sg.seed_chunks)
-            r_hi = r_lo + sg.seed_chunk_rows < sg.seed_rows ? r_lo + sg.seed_chunk_rows : sg.seed_rows;
-        else
-            r_hi = r_lo + sg.chunk_rows < N ? r_lo + sg.chunk_rows : N;
-    }
+    int64_t r_lo = 0, r_hi = 1;  // a wave past the last chunk loads row 0 and leaves after the set-up
+    if (active) chunk_rows_of(pidx, r_lo, r_hi);
     const uint4* __restrict__ pl = reinterpret_cast<const uint4*>(ix.plane);
     const int64_t p_lo = r_lo >> 1, p_last = ((r_hi + 1) >> 1) - 1;
     uint4 nx[kScanU];
-    if (active) {
 #pragma unroll
-        for (int u = 0; u < kScanU; ++u) {
-            const int64_t pp = p_lo + u * kWave + lane;
-            nx[u] = pl[pp < p_last ? pp : p_last];
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < kScanU; ++u) nx[u] = make_uint4(0u, 0u, 0u, 0u);
+    for (int u = 0; u < kScanU; ++u) {
+        const int64_t pp = p_lo + u * kWave + lane;
+        nx[u] = pl[pp < p_last ? pp : p_last];
     }
+    const uint64_t lim0 = lane_real ? lim_ld : kKeyMax;
+    uint64_t published = lim0;  // lane i: query i's limit as this wave last made it shared
 
     // LDS: [TQ][W] query words, the pre-filter (hashed variants), then per
     // wave [TQ] filters and [TQ][lstride] list entries
@@ -361,7 +379,13 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
             if (lane < ntq) {
                 const uint32_t* q = s_q + lane * W;
                 const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
-                limit_filter(lim0, chunk_lo(pidx0), q01, g, msk, qm);
+                int64_t first = N;  // the block's first row
+                for (int j = 0; j < kScanWaves && pidx0 + j < sg.nparts; ++j) {
+                    int64_t lo, hi;
+                    chunk_rows_of(pidx0 + j, lo, hi);
+                    first = lo < first ? lo : first;
+                }
+                limit_filter(lim0, first, q01, g, msk, qm);
             }
             // up to two mask lengths get a table; a query without a limit
             // (mask 0) or with another mask length is tested one by one
@@ -418,8 +442,8 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
         ScanFilter f;
         const bool is_real = lane < ntq;
         f.lim = lim0;
-        const int ki = k0;
-        f.kk = (int)((int64_t)ki < N ? (int64_t)ki : N);
+        const int ncap = N < 0x7fffffff ? (int)N : 0x7fffffff;
+        f.kk = is_real ? (k_ld < ncap ? k_ld : ncap) : 1;
         f.pad_ = 0;
         const uint32_t* q = s_q + lane * W;
         const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
@@ -458,8 +482,16 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
     int it = 0;
     for (int64_t base = r_lo; base < r_hi; base += kScanStepRows, ++it) {
         if (it > 0 && it % kGthrEvery == 0) {
-            // pick up tighter limits reached by other waves: lane i reads query
+            // publish the limits this wave tightened since the last time, and
+            // pick up tighter ones reached by other waves: lane i reads query
             // i's limit with a plain load (a stale value only prunes less)
+            if (lane < ntq) {
+                const uint64_t mylim = filt[lane].lim;
+                if (mylim < published) {
+                    atomicMin((unsigned long long*)(gthr + q0i + lane), (unsigned long long)mylim);
+                    published = mylim;
+                }
+            }
             const uint64_t mine = lane < ntq ? gthr[q0i + lane] : kKeyMax;
             bool changed = false;
 #pragma unroll 1
@@ -605,9 +637,18 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
                 const int e = r * kWave + lane;
                 lst.v[r] = e < sg.lstride ? lp[e] : kKeyMax;
             }
-            bool touched = false;
-#pragma unroll 1
+            // the rows with a candidate under the filter at entry (a superset:
+            // the filter only tightens below), then only those, in id order
+            uint32_t rows_todo = 0;
+#pragma unroll
             for (int t = 0; t < 2 * kScanU; ++t) {
+                const int64_t id = base + (t >> 1) * kPairRows + 2 * lane + (t & 1);
+                rows_todo |= ballot(id < r_hi && (v[t] & f.msk) == f.qm) ? 1u << t : 0u;
+            }
+            const bool touched = rows_todo != 0;
+#pragma unroll 1
+            for (; rows_todo; rows_todo &= rows_todo - 1) {
+                const int t = __builtin_ctz(rows_todo);
                 uint64_t w = v[0];
 #pragma unroll
                 for (int tt = 1; tt < 2 * kScanU; ++tt) w = t == tt ? v[tt] : w;
@@ -615,7 +656,6 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
                 const int64_t id = base + u * kPairRows + 2 * lane + h;
                 const bool cand = id < r_hi && (w & f.msk) == f.qm;
                 if (ballot(cand) == 0) continue;
-                touched = true;
                 int lc = -1;
                 if (cand) {
                     const uint64_t x = w ^ q01;
@@ -675,11 +715,11 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
             ++mine;
         }
     }
-    // limits this wave tightened go to the shared ones once, here (waves that
-    // start later read them)
+    // limits this wave tightened since it last published them go to the
+    // shared ones (waves that start later read them)
     if (lane < ntq) {
         const uint64_t mylim = filt[lane].lim;
-        if (mylim < lim0) atomicMin((unsigned long long*)(gthr + q0i + lane), (unsigned long long)mylim);
+        if (mylim < published) atomicMin((unsigned long long*)(gthr + q0i + lane), (unsigned long long)mylim);
     }
     uint32_t at = 0;
     if (lane < ntq && mine > 0) at = atomicAdd(cnt + (q0i + lane) * kCntStride, (uint32_t)mine);
@@ -851,6 +891,7 @@ constexpr int64_t kChunkMinRows = 2 * kScanStepRows;
 constexpr int64_t kSeedRows = 65536;
 constexpr int64_t kScanTargetWaves = 8192;  // 32 per CU
 constexpr int64_t kChunkAlign = kScanStepRows;  // main chunks: whole steps
+constexpr int64_t kSeedChunkRows = kScanStepRows;  // sampled rows per wave (while the grid allows)
 
 ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budget_bytes) {
     ScanPlan p;
@@ -870,8 +911,8 @@ ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budg
     }
     p.seed_rows = N < S ? N : S;
     // seed blocks per query: enough blocks in all to fill the device, but at
-    // most 32, since every block adds its counts to the query's histogram
-    // with global atomics on the same few addresses
+    // most 32 (the limit kernel gives each part a lane and sums the parts'
+    // histograms level by level)
     const int64_t seed_tiles = (p.seed_rows + 255) / 256;
     int64_t parts = Q > 0 ? 4096 / Q : 1;
     if (parts > 32) parts = 32;
@@ -886,13 +927,13 @@ ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budg
     }
     // sampled rows: one-step waves while the grid stays near the target,
     // fewer and longer ones for many query groups or a tight partial budget
-    int64_t sc = (p.seed_rows + kScanStepRows - 1) / kScanStepRows;
+    int64_t sc = (p.seed_rows + kSeedChunkRows - 1) / kSeedChunkRows;
     const int64_t by_grid = kScanTargetWaves / 2 / p.qgroups;
     if (sc > by_grid) sc = by_grid;
     if (sc > max_by_mem / 2) sc = max_by_mem / 2;
     if (sc < 1) sc = 1;
     p.seed_chunk_rows = (p.seed_rows + sc - 1) / sc;
-    p.seed_chunk_rows = (p.seed_chunk_rows + kScanStepRows - 1) / kScanStepRows * kScanStepRows;
+    p.seed_chunk_rows = (p.seed_chunk_rows + kSeedChunkRows - 1) / kSeedChunkRows * kSeedChunkRows;
     p.seed_chunks = (int)((p.seed_rows + p.seed_chunk_rows - 1) / p.seed_chunk_rows);
     // main: rows [seed_rows, N); aim for the target wave count, chunks of at
     // least kChunkMinRows rows (whole steps), partials within the budget
@@ -922,9 +963,10 @@ ScanScratch scan_scratch(const ScanPlan& p, int64_t Q, int32_t k_max, const RowG
     sc.gthr = base + (size_t)Q * (size_t)sc.cap;
     uint32_t* u = reinterpret_cast<uint32_t*>(sc.gthr + Q);
     sc.cnt = u;                                // [Q][kCntStride], entry 0 used; zeroed per call
-    sc.hist = u + (size_t)Q * kCntStride;      // [Q][L+1] zeroed per call
-    sc.qkeys = sc.hist + (size_t)Q * (g.L + 1);  // [Q][W]
-    sc.words = ((size_t)Q * (size_t)sc.cap + (size_t)Q) * 2 + (size_t)Q * (kCntStride + (g.L + 1) + g.W);
+    sc.hist = u + (size_t)Q * kCntStride;      // [Q][seed_parts][L+1], written whole by the seed blocks
+    sc.qkeys = sc.hist + (size_t)Q * p.seed_parts * (g.L + 1);  // [Q][W]
+    sc.words = ((size_t)Q * (size_t)sc.cap + (size_t)Q) * 2 +
+               (size_t)Q * (kCntStride + (size_t)p.seed_parts * (g.L + 1) + g.W);
     return sc;
 }
 
@@ -953,14 +995,14 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
                        hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
     if (qb.Q <= 0) return hipSuccess;
     const ScanScratch sc = scan_scratch(p, qb.Q, qb.k_max, ix.g, scratch);
-    const int64_t nz = qb.Q * (int64_t)(kCntStride + ix.g.L + 1);  // cnt and hist
+    const int64_t nz = qb.Q * (int64_t)kCntStride;  // the fill counts
     const int64_t nprep = nz > qb.Q * ix.g.W ? nz : qb.Q * ix.g.W;
     hipLaunchKernelGGL(k_scan_prep, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, s, qb, ix.g, sc.cnt, nz,
                        sc.qkeys);
     hipLaunchKernelGGL(k_seed_hist, dim3((unsigned)(qb.Q * p.seed_parts)), dim3(kSeedThreads), 0, s, ix, sc.qkeys,
                        p.seed_rows, p.seed_parts, sc.hist);
     hipLaunchKernelGGL(k_seed_limit, dim3((unsigned)((qb.Q + kScanWaves - 1) / kScanWaves)), dim3(kScanWaves * kWave),
-                       0, s, qb, ix.N, ix.g.L, p.seed_rows, sc.hist, sc.gthr);
+                       0, s, qb, ix.N, ix.g.L, p.seed_rows, p.seed_parts, sc.hist, sc.gthr);
     if (ev0) hipEventRecord(ev0, s);
     switch (p.nr * 1000 + p.tq * 10 + (p.hash ? 1 : 0)) {
         case 1641: launch_scan_t<1, 64, true>(ix, qb, p, sc, qb.k_max, s); break;
