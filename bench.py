@@ -413,50 +413,59 @@ def main():
         per_bucket = timed(lambda: [idx.topk(bq[kv], kv, out=bout[kv]) for kv in buckets])
         cur = torch.cuda.current_stream()
         per_bucket_dev = device_ms(lambda: [idx.topk(bq[kv], kv, out=bout[kv]) for kv in buckets], cur)
-        cl.q.copy_(q_dev)  # the batch is produced straight into the captured query buffer
+        # the batch is produced straight into the captured query buffer, in
+        # the tuned launch order (the answers keep the batch's own layout)
+        order = batching.launch_order(ku, w.Q, best.order)
+        cl.q.copy_(q_dev if order is None else q_dev[torch.from_numpy(order).to(dev)])
         torch.cuda.synchronize()
-        captured = timed(lambda: cl.run(None, ku, n=w.Q))
+        captured = timed(lambda: cl.run(None, ku, n=w.Q, order=order))
         reps_c = 20
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps_c)]
         for e in evs:
-            cl.run(None, ku, n=w.Q, events=e)
+            cl.run(None, ku, n=w.Q, events=e, order=order)
         torch.cuda.synchronize()
         captured_dev = float(np.median([a.elapsed_time(b) for a, b in evs]))
         ref = idx.topk(q_dev, ku, out=uo)
-        gi, gl, _ = cl.run(None, ku, n=w.Q)
+        gi, gl, _ = cl.run(None, ku, n=w.Q, order=order)
         torch.cuda.synchronize()
         same = bool(torch.equal(gi, ref.ids) and torch.equal(gl, ref.lcps))
         # the batch staged on the device ahead of time (as the per-bucket
         # launches have their queries and k ready): the replay alone
-        cl.stage(ku, w.Q)
+        cl.stage(ku, w.Q, order=order)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps_c)]
         for e in evs:
             cl.replay(events=e)
         torch.cuda.synchronize()
         staged_dev = float(np.median([a.elapsed_time(b) for a, b in evs]))
         # the same replay timed like the per-bucket launches: back-to-back on
-        # one stream between two events
-        staged_b2b = device_ms(lambda: cl.replay(), cur)
+        # one stream (the captured launch's own) between two events
+        def replays(reps=20):
+            cl.replay()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(cl.stream):
+                a.record(cl.stream)
+                for _ in range(reps):
+                    cl.graph.replay()
+                b.record(cl.stream)
+            b.synchronize()
+            return a.elapsed_time(b) / reps
+        staged_b2b = replays()
         staged_same = bool(torch.equal(cl.ids[:int(ku.sum())], ref.ids) and torch.equal(cl.lcps[:int(ku.sum())], ref.lcps))
         # every shape the autotuner tried, and the per-bucket launches, against the C oracle on all queries
         shapes_exact = None
         try:
             import oracle
             wi_u, wl_u, woff_u = oracle.c_topk(w.db, w.queries, ku)
-            kd = torch.from_numpy(ku).to(dev)
-            od = torch.from_numpy(woff_u).to(dev)
             cnt = torch.tensor([w.Q], dtype=torch.int64, device=dev)
             shapes_exact = {}
             for sh in tune["tried"]:
                 si = torch.full_like(uo[0], -9)
                 sl = torch.full_like(uo[1], -9)
-                if sh.mode == "plain":
-                    idx.topk_dev(q_dev, kd, od, 100, si, sl)
-                else:
-                    idx.topk_persistent(q_dev, cnt, kd, od, 100, si, sl, blocks=sh.blocks)
+                batching.run_shape(idx, sh, batching.shape_inputs(q_dev, ku, sh.order), 100, si, sl, cnt)
                 torch.cuda.synchronize()
-                shapes_exact[f"{sh.mode}:{sh.blocks}"] = bool((si.cpu().numpy() == wi_u).all() and
-                                                              (sl.cpu().numpy() == wl_u).all())
+                shapes_exact[f"{sh.mode}:{sh.blocks}:{sh.order}"] = bool((si.cpu().numpy() == wi_u).all() and
+                                                                         (sl.cpu().numpy() == wl_u).all())
             bucket_ok = True
             for kv, sel in buckets.items():
                 bi = bout[kv][0].cpu().numpy().reshape(-1, kv)
@@ -477,9 +486,9 @@ def main():
                                           "captured_staged_replay": round(staged_b2b, 4)},
                   "captured_staged_replay_equals_plain": staged_same,
                   "oracle_exact_by_shape": shapes_exact,
-                  "captured_shape": (tune["best"].mode, tune["best"].blocks),
+                  "captured_shape": (tune["best"].mode, tune["best"].blocks, tune["best"].order),
                   "captured_qps": round(w.Q / (captured * 1e-3), 1),
-                  "autotune": [(sh.mode, sh.blocks, round(sh.ms, 4)) for sh in tune["tried"]],
+                  "autotune": [(sh.mode, sh.blocks, sh.order, round(sh.ms, 4)) for sh in tune["tried"]],
                   "captured_equals_plain": same}
         log(args, f"[bench] uneven batch: {uneven}")
 

@@ -10,8 +10,16 @@ has one wave per query of the capacity; a smaller persistent grid, whose waves
 loop over queries from a device work counter, can be chosen instead.
 
 `tune_launch` is the autotuner: it times the plain launch, the one-wave-per-
-query counted launch and persistent grids of several sizes on a sample batch
+query counted launch and persistent grids of several sizes, each with the
+queries in their own order and with the largest k first, on a sample batch,
 and returns the fastest shape.
+
+Query order.  Every query's answer goes to its own offset, so a batch may be
+launched in any order of its queries without moving the answers: staging the
+queries, their k and their offsets in the same permuted order leaves the
+output layout as it is.  With the largest k first, the longest waves start
+first and the short ones fill the device at the end of the launch (longest-
+processing-time-first order).
 """
 from __future__ import annotations
 
@@ -29,6 +37,18 @@ class LaunchShape:
     mode: str          # "plain", "counted" (one wave per query) or "persistent" (waves loop)
     blocks: int = 0    # grid size in blocks of 4 waves (0 = one wave per query)
     ms: float = float("nan")
+    order: str = "given"  # "given" or "k_desc" (largest k first)
+
+
+def launch_order(k, n: int, order: str) -> Optional[np.ndarray]:
+    """The permutation a shape launches the batch in (None: as given).
+    Stable, so equal k keep their relative order."""
+    if order == "given":
+        return None
+    if order != "k_desc":
+        raise ValueError(f"unknown query order {order!r}")
+    ks = np.broadcast_to(np.asarray(k, dtype=np.int32), (n,))
+    return np.argsort(-ks, kind="stable")
 
 
 class CapturedLaunch:
@@ -83,10 +103,13 @@ class CapturedLaunch:
         self.index.topk_persistent(self.q, self.count, self.k, self.off, self.k_max, self.ids, self.lcps,
                                    blocks=self.blocks, stream=self.stream)
 
-    def stage(self, k, n: int) -> np.ndarray:
+    def stage(self, k, n: int, order: Optional[np.ndarray] = None) -> np.ndarray:
         """Put a batch's size, offsets and k into the device buffers ahead of a
         replay (for producers that prepare batches before they are due);
-        returns the offsets.  The queries go into the first n rows of `self.q`."""
+        returns the offsets of the answers (in the batch's own order).  The
+        queries go into the first n rows of `self.q`; with `order`, row j
+        holds query order[j] and the answers still land at the batch's own
+        offsets."""
         if self.index.generation() != self.generation:
             raise RuntimeError("the index has been appended to since this launch was captured; capture it again")
         n = int(n)
@@ -100,8 +123,13 @@ class CapturedLaunch:
         host = torch.zeros(self._nbytes, dtype=torch.uint8)
         hc, ho, hk = (v.numpy() for v in self._views(host))
         hc[0] = n
-        ho[:n + 1] = off
-        hk[:n] = ks
+        if order is None:
+            ho[:n + 1] = off
+            hk[:n] = ks
+        else:
+            ho[:n] = off[:n][order]
+            ho[n] = off[n]
+            hk[:n] = ks[order]
         with torch.cuda.stream(self.stream):
             self.dbuf.copy_(host.to(self.dbuf.device))
         self.stream.synchronize()
@@ -122,11 +150,14 @@ class CapturedLaunch:
         cur.wait_stream(self.stream)
 
     def run(self, queries: Optional[torch.Tensor], k, n: Optional[int] = None,
-            events=None) -> "tuple[torch.Tensor, torch.Tensor, np.ndarray]":
+            events=None, order: Optional[np.ndarray] = None) -> "tuple[torch.Tensor, torch.Tensor, np.ndarray]":
         """Answer `queries` (device [n, L]) with per-query k (host); returns
-        (ids, lcps, offsets) views valid until the next run.  With queries
-        None the first n rows of `self.q`, filled by the caller, are used.
-        `events` = (start, end) are recorded around the device work."""
+        (ids, lcps, offsets) views valid until the next run, in the batch's
+        own order.  With queries None the first n rows of `self.q`, filled
+        by the caller, are used (row j holding query order[j] when an order
+        is given).  With `order` the queries are launched in that order (see
+        `launch_order`).  `events` = (start, end) are recorded around the
+        device work."""
         if self.index.generation() != self.generation:
             raise RuntimeError("the index has been appended to since this launch was captured; capture it again")
         n = int(queries.shape[0]) if queries is not None else int(n)
@@ -143,6 +174,12 @@ class CapturedLaunch:
         ho[0] = 0
         np.cumsum(ks, out=ho[1:n + 1])
         hk[:n] = ks
+        answer_off = ho[:n + 1].copy()
+        if order is not None:
+            ho[:n] = answer_off[:n][order]
+            hk[:n] = ks[order]
+            if queries is not None:
+                queries = queries[torch.from_numpy(np.asarray(order)).to(queries.device)]
         cur = torch.cuda.current_stream()
         self.stream.wait_stream(cur)  # the queries were produced on the caller's stream
         with torch.cuda.stream(self.stream):
@@ -156,8 +193,8 @@ class CapturedLaunch:
             if events is not None:
                 events[1].record(self.stream)
         cur.wait_stream(self.stream)
-        total = int(ho[n])
-        return self.ids[:total], self.lcps[:total], ho[:n + 1].copy()
+        total = int(answer_off[n])
+        return self.ids[:total], self.lcps[:total], answer_off
 
 
 def _time_ms(fn, reps: int) -> float:
@@ -174,34 +211,56 @@ def _time_ms(fn, reps: int) -> float:
     return float(np.median(times))
 
 
+def shape_inputs(queries: torch.Tensor, k, order: str):
+    """(queries, k, offsets) on the device as a shape launches them: in the
+    shape's query order, each query's offset still its place in the batch's
+    own answer layout."""
+    n = int(queries.shape[0])
+    ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (n,)))
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(ks, out=off[1:])
+    perm = launch_order(ks, n, order)
+    dev = queries.device
+    if perm is None:
+        return queries, torch.from_numpy(ks).to(dev), torch.from_numpy(off).to(dev)
+    po = np.append(off[:n][perm], off[n])
+    pt = torch.from_numpy(perm).to(dev)
+    return queries[pt].contiguous(), torch.from_numpy(ks[perm].copy()).to(dev), torch.from_numpy(po).to(dev)
+
+
+def run_shape(index, sh: LaunchShape, inputs, kmax: int, ids: torch.Tensor, lcps: torch.Tensor,
+              count: torch.Tensor) -> None:
+    """One launch of shape `sh` on `shape_inputs(...)` for its order."""
+    q, k_dev, off_dev = inputs
+    if sh.mode == "plain":
+        index.topk_dev(q, k_dev, off_dev, kmax, ids, lcps)
+    else:
+        index.topk_persistent(q, count, k_dev, off_dev, kmax, ids, lcps, blocks=sh.blocks)
+
+
 def tune_launch(index, queries: torch.Tensor, k, reps: int = 7, cus: Optional[int] = None) -> Dict:
     """Time the plain launch, the one-wave-per-query counted launch and
-    persistent grids of 1, 2 and 4 blocks per CU on one batch; return
+    persistent grids of 1, 2 and 4 blocks per CU on one batch, each with the
+    queries in their given order and with the largest k first; return
     {"best": LaunchShape, "tried": [LaunchShape, ...]}."""
     n = int(queries.shape[0])
     ks = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (n,)))
     kmax = int(ks.max())
     dev = index.device
-    off = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(ks, out=off[1:])
-    k_dev = torch.from_numpy(ks).to(dev)
-    off_dev = torch.from_numpy(off).to(dev)
     count = torch.tensor([n], dtype=torch.int64, device=dev)
-    ids = torch.empty(int(off[-1]), dtype=torch.int32, device=dev)
+    ids = torch.empty(int(ks.sum()), dtype=torch.int32, device=dev)
     lcps = torch.empty_like(ids)
     if cus is None:
         cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    shapes = [LaunchShape("plain", 0), LaunchShape("counted", 0)]
+    shapes += [LaunchShape("persistent", cus * m) for m in (1, 2, 4) if 4 * cus * m < n]  # larger: the counted launch
     tried: List[LaunchShape] = []
-    tried.append(LaunchShape("plain", 0, _time_ms(
-        lambda: index.topk_dev(queries, k_dev, off_dev, kmax, ids, lcps), reps)))
-    tried.append(LaunchShape("counted", 0, _time_ms(
-        lambda: index.topk_persistent(queries, count, k_dev, off_dev, kmax, ids, lcps, blocks=0), reps)))
-    for mult in (1, 2, 4):
-        b = cus * mult
-        if 4 * b >= n:
-            continue  # that grid is the counted launch
-        tried.append(LaunchShape("persistent", b, _time_ms(
-            lambda: index.topk_persistent(queries, count, k_dev, off_dev, kmax, ids, lcps, blocks=b), reps)))
+    for order in ("given", "k_desc"):
+        inputs = shape_inputs(queries, ks, order)
+        for base in shapes:
+            sh = LaunchShape(base.mode, base.blocks, order=order)
+            sh.ms = _time_ms(lambda: run_shape(index, sh, inputs, kmax, ids, lcps, count), reps)
+            tried.append(sh)
     best = min(tried, key=lambda s: s.ms)
     return {"best": best, "tried": tried}
 

@@ -160,8 +160,10 @@ __global__ __launch_bounds__(kScanWaves * kWave) void k_seed_limit(QueryBatch qb
     for (int top = L; top >= 0; top -= kWave) {
         const int d = top - lane;
         uint32_t c = 0;
-        if (d >= 0)
+        if (d >= 0) {
+#pragma unroll 8
             for (int p = 0; p < parts; ++p) c += h[(int64_t)p * (L + 1) + d];
+        }
         const uint32_t acc = wave_prefix_sum(c) + above;
         const uint64_t ok = ballot(d >= 0 && acc >= kk);
         if (ok) {
@@ -911,11 +913,11 @@ ScanPlan plan_scan(int64_t N, int W, int64_t Q, int32_t k_max, int64_t part_budg
     }
     p.seed_rows = N < S ? N : S;
     // seed blocks per query: enough blocks in all to fill the device, but at
-    // most 32 (the limit kernel gives each part a lane and sums the parts'
+    // most 64 (the limit kernel gives each part a lane and sums the parts'
     // histograms level by level)
     const int64_t seed_tiles = (p.seed_rows + 255) / 256;
     int64_t parts = Q > 0 ? 4096 / Q : 1;
-    if (parts > 32) parts = 32;
+    if (parts > kWave) parts = kWave;
     if (parts > seed_tiles) parts = seed_tiles;
     p.seed_parts = (int)(parts < 1 ? 1 : parts);
     const int64_t bytes_per_chunk = Q * (int64_t)k_max * 8;

@@ -478,18 +478,43 @@ def test_autotuned_shapes_agree(P):
         res = batching.tune_launch(idx, qd, w.k, reps=2)
         assert res["best"].ms == min(s.ms for s in res["tried"])
         ref = idx.topk(qd, w.k)
-        kd = torch.from_numpy(w.k).cuda()
-        od = torch.from_numpy(ref.offsets).cuda()
         cnt = torch.tensor([w.Q], dtype=torch.int64, device="cuda")
+        assert {s.order for s in res["tried"]} == {"given", "k_desc"}
         for shape in res["tried"]:
             ids = torch.full_like(ref.ids, -9)
             lcps = torch.full_like(ref.lcps, -9)
-            if shape.mode == "plain":
-                idx.topk_dev(qd, kd, od, 100, ids, lcps)
-            else:
-                idx.topk_persistent(qd, cnt, kd, od, 100, ids, lcps, blocks=shape.blocks)
+            batching.run_shape(idx, shape, batching.shape_inputs(qd, w.k, shape.order), 100, ids, lcps, cnt)
             torch.cuda.synchronize()
             assert torch.equal(ids, ref.ids) and torch.equal(lcps, ref.lcps), shape
+        wi, wl, woff = oracle.c_topk(w.db, w.queries, w.k)
+        assert (ref.ids.cpu().numpy() == wi).all() and (ref.lcps.cpu().numpy() == wl).all()
+
+
+def test_captured_launch_in_largest_k_first_order(P):
+    """A captured launch fed its batch with the largest k first (queries, k
+    and offsets permuted together, by run and by stage + replay) answers in
+    the batch's own layout, equal to the oracle for every query."""
+    import torch
+    from paper_2602_04936_amd import batching
+    w = synth.c3_like(200_000, 2000, seed=14)
+    qd = P.to_device_tokens(w.queries)
+    wi, wl, woff = oracle.c_topk(w.db, w.queries, w.k)
+    with P.Index(w.db, w.V) as idx:
+        cl = batching.CapturedLaunch(idx, cap_queries=2000, k_max=100)
+        for n in (2000, 777):
+            order = batching.launch_order(w.k[:n], n, "k_desc")
+            assert (np.diff(w.k[:n][order]) <= 0).all()
+            ids, lcps, off = cl.run(qd[:n], w.k[:n], order=order)
+            torch.cuda.synchronize()
+            tot = int(w.k[:n].sum())
+            assert (off == woff[:n + 1]).all()
+            assert (ids.cpu().numpy() == wi[:tot]).all() and (lcps.cpu().numpy() == wl[:tot]).all(), n
+        order = batching.launch_order(w.k, 2000, "k_desc")
+        cl.q.copy_(qd[torch.from_numpy(order).cuda()])
+        cl.stage(w.k, 2000, order=order)
+        cl.replay()
+        torch.cuda.synchronize()
+        assert (cl.ids[:woff[-1]].cpu().numpy() == wi).all() and (cl.lcps[:woff[-1]].cpu().numpy() == wl).all()
 
 
 def test_append_large_batch_and_after_a_rejected_one(P):
