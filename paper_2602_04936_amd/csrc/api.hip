@@ -727,7 +727,7 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
             a.cap = kRankSortMax;
         }
         HIP_TRY(launch_pack_keys(tokens, n, g, (uint32_t)idx->V, newkeys, a.flag, epoch, s));
-        HIP_TRY(launch_rank_sort(newkeys, n, W, a.sorted, a.lperm, s));
+        HIP_TRY(launch_rank_ub(newkeys, n, src.sorted, N, W, a.sorted, a.lperm, a.ub, s));
         nsorted = a.sorted;
         nperm = a.lperm;
         ub = a.ub;
@@ -742,12 +742,12 @@ lcp_status append_into(lcp_index* idx, const void* tokens, int64_t n, hipStream_
         nperm = big.perm;
         ub = big.ub;
     }
-    HIP_TRY(launch_upper_bounds(src.sorted, N, nsorted, n, g, ub, s));
+    if (n > kRankSortMax) HIP_TRY(launch_upper_bounds(src.sorted, N, nsorted, n, g, ub, s));
     HIP_TRY(launch_merge_sorted(src.sorted, src.perm, src.A, N, nsorted, nperm, ub, n, g, dst.sorted, dst.perm,
                                 dst.A, s));
     const int levels = search_table_levels(M);
-    if (levels > 0) HIP_TRY(launch_search_tables(dst.sorted, M, W, levels, dst.stab, s));
-    HIP_TRY(launch_append_tail(dst.perm, dst.sorted, M, g, idx->V, rows, N, dst.bmin, dst.dir, plane, s));
+    HIP_TRY(launch_append_tail(dst.perm, dst.sorted, M, g, idx->V, rows, N, dst.bmin, dst.dir, plane, levels, dst.stab,
+                               s));
     HIP_TRY(hipMemcpyAsync(a.flag_host, a.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (*a.flag_host == epoch) return fail(LCP_ERANGE, "a token is >= V = %d", idx->V);  // index unchanged

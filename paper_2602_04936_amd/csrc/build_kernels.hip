@@ -364,9 +364,8 @@ __global__ void k_block_min(const int32_t* __restrict__ perm, int64_t N, uint32_
     if (lane_id() == 0) bmin[b] = v;
 }
 
-__global__ void k_search_tables(const uint32_t* __restrict__ sorted, int64_t N, int W, int levels,
-                                uint4* __restrict__ stab) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void search_table_entry(int64_t t, const uint32_t* __restrict__ sorted, int64_t N, int W,
+                                                   int levels, uint4* __restrict__ stab) {
     int64_t total = 1;
     for (int d = 0; d < levels; ++d) total *= kWave + 1;
     if (t >= total - 1) return;
@@ -409,6 +408,11 @@ __global__ void k_search_tables(const uint32_t* __restrict__ sorted, int64_t N, 
     stab[t] = key;
 }
 
+__global__ void k_search_tables(const uint32_t* __restrict__ sorted, int64_t N, int W, int levels,
+                                uint4* __restrict__ stab) {
+    search_table_entry((int64_t)blockIdx.x * blockDim.x + threadIdx.x, sorted, N, W, levels, stab);
+}
+
 // ------------------------------------------------------------ append (merge)
 
 // -1, 0, +1: order of two key-form rows
@@ -436,99 +440,82 @@ __global__ void k_upper_bounds(const uint32_t* __restrict__ sorted, int64_t N, c
     ub[j] = lo;
 }
 
-// Stable sort of n new rows by rank: row j goes to position #{i : row i <
-// row j, or row i == row j and i < j}.  Rows are compared by their first two
-// key words as one 64-bit value (word 0 high), and by the remaining words only
-// where those agree.  Each block stages tiles of the rows' leading values in
-// LDS and every thread counts, for its own row, the rows of the tile ranked
-// before it.  O(n^2) compares of one 64-bit value: used for small appends.
-constexpr int kRankThreads = 64;
-constexpr int kRankTile = 1024;
-__global__ __launch_bounds__(kRankThreads) void k_rank_sort(const uint32_t* __restrict__ keys, int64_t n, int W,
-                                                            uint32_t* __restrict__ sorted,
-                                                            int32_t* __restrict__ lperm) {
-    __shared__ uint64_t tile[kRankTile];
-    const int64_t j = (int64_t)blockIdx.x * kRankThreads + threadIdx.x;
-    const bool act = j < n;
-    const uint32_t* mine = keys + (act ? j : 0) * W;
+// Small appends, one wave per new row j (n <= kRankSortMax):
+//  - its rank among the new rows: #{i : row i < row j, or row i == row j and
+//    i < j}, 64 rows per ballot, their leading 64 bits compared first and the
+//    remaining words only where those agree (a stable sort by rank);
+//  - its upper bound among the old sorted rows (the number of old rows <= it;
+//    old rows equal to it come first: they have smaller ids) by a 65-ary
+//    search: 64 lanes compare 64 pivots per step, ceil(log65 N) steps;
+//  - the row, its local id and its upper bound written at its rank.
+__device__ __forceinline__ int compare_tail(const uint32_t* a, const uint32_t* b, int from, int W) {
+    for (int w = from; w < W; ++w)
+        if (a[w] != b[w]) return a[w] < b[w] ? -1 : 1;
+    return 0;
+}
+
+constexpr int kRankUbWaves = 4;
+constexpr int kRankUnroll = 8;
+__global__ __launch_bounds__(kRankUbWaves * kWave) void k_rank_ub(const uint32_t* __restrict__ keys, int64_t n,
+                                                                  const uint32_t* __restrict__ old_sorted,
+                                                                  int64_t N, int W, uint32_t* __restrict__ sorted,
+                                                                  int32_t* __restrict__ lperm,
+                                                                  int64_t* __restrict__ ub) {
+    const int lane = lane_id();
+    const int64_t j = (int64_t)blockIdx.x * kRankUbWaves + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (j >= n) return;  // whole waves leave together
+    const uint32_t* mine = keys + j * W;
     const uint64_t pj = ((uint64_t)mine[0] << 32) | (W > 1 ? mine[1] : 0u);
+    // rank: kRankUnroll groups of 64 rows per round, all loads in flight first
     int64_t rank = 0;
-    for (int64_t t0 = 0; t0 < n; t0 += kRankTile) {
-        const int tn = (int)(n - t0 < kRankTile ? n - t0 : kRankTile);
-        __syncthreads();
-        for (int e = threadIdx.x; e < tn; e += kRankThreads) {
-            const uint32_t* o = keys + (t0 + e) * W;
-            tile[e] = ((uint64_t)o[0] << 32) | (W > 1 ? o[1] : 0u);
+    for (int64_t b = 0; b < n; b += (int64_t)kRankUnroll * kWave) {
+        uint64_t pv[kRankUnroll];
+#pragma unroll
+        for (int u = 0; u < kRankUnroll; ++u) {
+            const int64_t i = b + u * kWave + lane;
+            const uint32_t* o = keys + (i < n ? i : 0) * W;
+            pv[u] = ((uint64_t)o[0] << 32) | (W > 1 ? o[1] : 0u);
         }
-        __syncthreads();
-        if (act) {
-            for (int r = 0; r < tn; ++r) {
-                const uint64_t pi = tile[r];
-                int c = pi < pj ? -1 : pi > pj ? 1 : 0;
-                const int64_t i = t0 + r;
-                if (c == 0 && i != j) {  // the leading words agree: the rest decides
-                    const uint32_t* o = keys + i * W;
-                    for (int w = 2; w < W && c == 0; ++w) c = o[w] < mine[w] ? -1 : o[w] > mine[w] ? 1 : 0;
-                }
-                rank += (c < 0 || (c == 0 && i < j)) ? 1 : 0;
-            }
+#pragma unroll
+        for (int u = 0; u < kRankUnroll; ++u) {
+            const int64_t i = b + u * kWave + lane;
+            const bool act = i < n;
+            int c = pv[u] < pj ? -1 : pv[u] > pj ? 1 : 0;
+            if (act && c == 0 && i != j && W > 2) c = compare_tail(keys + i * W, mine, 2, W);
+            rank += popc64(ballot(act && (c < 0 || (c == 0 && i < j))));
         }
     }
-    if (!act) return;
-    lperm[rank] = (int32_t)j;
-    for (int w = 0; w < W; ++w) sorted[rank * W + w] = mine[w];
-}
-
-// Old row i moves right by the number of new rows placed before it: those
-// with ub <= i (ub is non-decreasing along the sorted new rows).  Its id and
-// adjacent LCP go along; the LCP stays right unless a new row now precedes it,
-// which k_seam_lcp repairs.  One thread per old row finds the shift, then the
-// block copies its rows word by word.
-constexpr int kMergeThreads = 256;
-__global__ __launch_bounds__(kMergeThreads) void k_merge_old(const uint32_t* __restrict__ sorted,
-                                                             const int32_t* __restrict__ perm,
-                                                             const uint8_t* __restrict__ A, int64_t N,
-                                                             const int64_t* __restrict__ ub, int64_t n, int W,
-                                                             uint32_t* __restrict__ out_sorted,
-                                                             int32_t* __restrict__ out_perm,
-                                                             uint8_t* __restrict__ out_A) {
-    __shared__ int64_t shift[kMergeThreads];
-    const int64_t i0 = (int64_t)blockIdx.x * kMergeThreads;
-    const int64_t i = i0 + threadIdx.x;
-    int64_t lo = 0;
-    if (i < N) {
-        int64_t hi = n;
-        while (lo < hi) {
-            const int64_t mid = lo + (hi - lo) / 2;
-            if (ub[mid] <= i)
-                lo = mid + 1;
-            else
-                hi = mid;
+    // upper bound among the old rows
+    int64_t lo = 0, hi = N;
+    while (hi - lo > kWave) {
+        const int64_t len = hi - lo;
+        const int64_t a65 = len / (kWave + 1), b65 = len - (kWave + 1) * a65;
+        const int64_t pos = lo + (lane + 1) * a65 + ((lane + 1) * b65) / (kWave + 1);
+        const uint32_t* o = old_sorted + pos * W;
+        const uint64_t po = ((uint64_t)o[0] << 32) | (W > 1 ? o[1] : 0u);
+        int c = po < pj ? -1 : po > pj ? 1 : 0;
+        if (c == 0 && W > 2) c = compare_tail(o, mine, 2, W);
+        const int cnt = popc64(ballot(c <= 0));  // pivots <= the row: a prefix of the lanes
+        const int64_t lo0 = lo;
+        if (cnt > 0) lo = lo0 + cnt * a65 + (cnt * b65) / (kWave + 1) + 1;
+        if (cnt < kWave) hi = lo0 + (cnt + 1) * a65 + ((cnt + 1) * b65) / (kWave + 1);
+    }
+    {
+        const int64_t pos = lo + lane;
+        int c = 1;
+        if (pos < hi) {
+            const uint32_t* o = old_sorted + pos * W;
+            const uint64_t po = ((uint64_t)o[0] << 32) | (W > 1 ? o[1] : 0u);
+            c = po < pj ? -1 : po > pj ? 1 : 0;
+            if (c == 0 && W > 2) c = compare_tail(o, mine, 2, W);
         }
-        out_perm[i + lo] = perm[i];
-        out_A[i + lo] = A[i];
+        lo += popc64(ballot(pos < hi && c <= 0));
     }
-    shift[threadIdx.x] = lo;
-    __syncthreads();
-    const int64_t rows = N - i0 < kMergeThreads ? N - i0 : kMergeThreads;
-    for (int64_t t = threadIdx.x; t < rows * W; t += kMergeThreads) {
-        const int64_t r = t / W;
-        const int64_t w = t - r * W;
-        out_sorted[(i0 + r + shift[r]) * W + w] = sorted[i0 * W + t];
+    for (int w = lane; w < W; w += kWave) sorted[rank * W + w] = mine[w];
+    if (lane == 0) {
+        lperm[rank] = (int32_t)j;
+        ub[rank] = lo;
     }
-}
-
-// One thread per (new row, word): sorted new row j goes to ub[j] + j.
-__global__ void k_merge_new(const uint32_t* __restrict__ newrows, const int32_t* __restrict__ newperm, int64_t N,
-                            const int64_t* __restrict__ ub, int64_t n, int W, uint32_t* __restrict__ out_sorted,
-                            int32_t* __restrict__ out_perm) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * W) return;
-    const int64_t j = t / W;
-    const int64_t w = t - j * W;
-    const int64_t dst = ub[j] + j;
-    out_sorted[dst * W + w] = newrows[t];
-    if (w == 0) out_perm[dst] = (int32_t)(N + newperm[j]);
 }
 
 __device__ __forceinline__ int row_lcp(const uint32_t* a, const uint32_t* b, const RowGeo& g) {
@@ -539,17 +526,72 @@ __device__ __forceinline__ int row_lcp(const uint32_t* a, const uint32_t* b, con
     return g.L;
 }
 
-// The adjacent LCP where a new row was inserted: at its own position (against
-// the row before it) and at the next position (the row after it now follows
-// it).  Every position whose predecessor changed is one of these.
-__global__ void k_seam_lcp(const uint32_t* __restrict__ merged, int64_t M, const int64_t* __restrict__ ub, int64_t n,
-                           RowGeo g, uint8_t* __restrict__ A) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// The merge of the new rows into a sorted copy, in one launch by block
+// ranges.  Blocks [0, nb_old) move the old rows: old row i moves right by the
+// number of new rows placed before it (those with ub <= i; ub is
+// non-decreasing along the sorted new rows), one thread per row finds that
+// shift and the block copies its rows word by word; the row's id goes along,
+// and its adjacent LCP too unless a new row now precedes it.  The next nb_new
+// blocks place sorted new row j at ub[j] + j, one thread per (row, word).
+// The rest compute the adjacent LCP at and
+// right after each new row from the source rows themselves (the merged
+// neighbours of new row j at P = ub[j] + j are new row j - 1 when it has the
+// same upper bound, else old row ub[j] - 1, and new row j + 1 when it has the
+// same upper bound, else old row ub[j]), so no block reads another's output.
+constexpr int kMergeThreads = 256;
+__global__ __launch_bounds__(kMergeThreads) void k_merge_fused(
+    const uint32_t* __restrict__ sorted, const int32_t* __restrict__ perm, const uint8_t* __restrict__ A, int64_t N,
+    const uint32_t* __restrict__ newrows, const int32_t* __restrict__ newperm, const int64_t* __restrict__ ub,
+    int64_t n, RowGeo g, uint32_t* __restrict__ out_sorted, int32_t* __restrict__ out_perm,
+    uint8_t* __restrict__ out_A, unsigned nb_old, unsigned nb_new) {
+    __shared__ int64_t shift[kMergeThreads];
+    const int W = g.W;
+    const unsigned b = blockIdx.x;
+    if (b < nb_old) {
+        const int64_t i0 = (int64_t)b * kMergeThreads;
+        const int64_t i = i0 + threadIdx.x;
+        int64_t lo = 0;
+        if (i < N) {
+            int64_t hi = n;
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (ub[mid] <= i)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            out_perm[i + lo] = perm[i];
+            if (!(lo > 0 && ub[lo - 1] == i)) out_A[i + lo] = A[i];  // else a new row precedes it
+        }
+        shift[threadIdx.x] = lo;
+        __syncthreads();
+        const int64_t rows = N - i0 < kMergeThreads ? N - i0 : kMergeThreads;
+        for (int64_t t = threadIdx.x; t < rows * W; t += kMergeThreads) {
+            const int64_t r = t / W;
+            const int64_t w = t - r * W;
+            out_sorted[(i0 + r + shift[r]) * W + w] = sorted[i0 * W + t];
+        }
+        return;
+    }
+    if (b < nb_old + nb_new) {
+        const int64_t t = (int64_t)(b - nb_old) * kMergeThreads + threadIdx.x;
+        if (t >= n * W) return;
+        const int64_t j = t / W;
+        const int64_t w = t - j * W;
+        const int64_t dst = ub[j] + j;
+        out_sorted[dst * W + w] = newrows[t];
+        if (w == 0) out_perm[dst] = (int32_t)(N + newperm[j]);
+        return;
+    }
+    const int64_t j = (int64_t)(b - nb_old - nb_new) * kMergeThreads + threadIdx.x;
     if (j >= n) return;
-    const int64_t P = ub[j] + j;
-    const uint32_t* row = merged + P * g.W;
-    A[P] = P == 0 ? 0 : (uint8_t)row_lcp(row - g.W, row, g);
-    if (P + 1 < M) A[P + 1] = (uint8_t)row_lcp(row, row + g.W, g);
+    const int64_t u = ub[j];
+    const int64_t P = u + j;
+    const uint32_t* row = newrows + j * W;
+    const uint32_t* pred = j > 0 && ub[j - 1] == u ? newrows + (j - 1) * W : u > 0 ? sorted + (u - 1) * W : nullptr;
+    out_A[P] = pred ? (uint8_t)row_lcp(pred, row, g) : 0;
+    const uint32_t* succ = j + 1 < n && ub[j + 1] == u ? newrows + (j + 1) * W : u < N ? sorted + u * W : nullptr;
+    if (succ) out_A[P + 1] = (uint8_t)row_lcp(row, succ, g);
 }
 
 // ------------------------------------------------------------ launchers
@@ -564,11 +606,10 @@ hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, cons
                                const uint32_t* newrows, const int32_t* newperm, const int64_t* ub, int64_t n, RowGeo g,
                                uint32_t* out_sorted, int32_t* out_perm, uint8_t* out_A, hipStream_t s) {
     const int W = g.W;
-    hipLaunchKernelGGL(k_merge_old, dim3(blocks_for(N, kMergeThreads)), dim3(kMergeThreads), 0, s, sorted, perm, A, N,
-                       ub, n, W, out_sorted, out_perm, out_A);
-    hipLaunchKernelGGL(k_merge_new, dim3(blocks_for(n * W, 256)), dim3(256), 0, s, newrows, newperm, N, ub, n, W,
-                       out_sorted, out_perm);
-    hipLaunchKernelGGL(k_seam_lcp, dim3(blocks_for(n, 256)), dim3(256), 0, s, out_sorted, N + n, ub, n, g, out_A);
+    const unsigned nb_old = blocks_for(N, kMergeThreads), nb_new = blocks_for(n * W, kMergeThreads);
+    const unsigned nb_seam = blocks_for(n, kMergeThreads);
+    hipLaunchKernelGGL(k_merge_fused, dim3(nb_old + nb_new + nb_seam), dim3(kMergeThreads), 0, s, sorted, perm, A, N,
+                       newrows, newperm, ub, n, g, out_sorted, out_perm, out_A, nb_old, nb_new);
     return hipGetLastError();
 }
 
@@ -584,8 +625,12 @@ hipError_t launch_first_token_dir(const uint32_t* sorted, int64_t N, RowGeo g, i
 __global__ void k_append_tail(const int32_t* __restrict__ perm, const uint32_t* __restrict__ sorted, int64_t M,
                               RowGeo g, int V, const uint32_t* __restrict__ rows, int64_t from,
                               uint32_t* __restrict__ bmin, uint32_t* __restrict__ dir, uint64_t* __restrict__ plane,
-                              unsigned nb, unsigned nd) {
-    const unsigned b = blockIdx.x;
+                              int levels, uint4* __restrict__ stab, unsigned ns, unsigned nb, unsigned nd) {
+    if (blockIdx.x < ns) {
+        search_table_entry((int64_t)blockIdx.x * blockDim.x + threadIdx.x, sorted, M, g.W, levels, stab);
+        return;
+    }
+    const unsigned b = blockIdx.x - ns;
     if (b < nb) {
         const int64_t blk = (int64_t)b * (blockDim.x / kWave) + (threadIdx.x / kWave);
         if (blk >= (M + kWave - 1) / kWave) return;  // whole waves leave together
@@ -616,19 +661,22 @@ __global__ void k_append_tail(const int32_t* __restrict__ perm, const uint32_t* 
 
 hipError_t launch_append_tail(const int32_t* perm, const uint32_t* sorted, int64_t M, RowGeo g, int V,
                               const uint32_t* rows, int64_t from, uint32_t* bmin, uint32_t* dir, uint64_t* plane,
-                              hipStream_t s) {
+                              int levels, uint4* stab, hipStream_t s) {
+    const int64_t nst = levels > 0 ? search_table_entries(levels) : 0;
+    const unsigned ns = nst > 0 ? blocks_for(nst, 256) : 0u;
     const unsigned nb = blocks_for(block_min_entries(M), 256 / kWave);
     const unsigned nd = blocks_for((int64_t)V + 2, 256);
     const int64_t np = plane_entries(M) - from;
     const unsigned npb = np > 0 ? blocks_for(np, 256) : 0u;
-    hipLaunchKernelGGL(k_append_tail, dim3(nb + nd + npb), dim3(256), 0, s, perm, sorted, M, g, V, rows, from, bmin, dir,
-                       plane, nb, nd);
+    hipLaunchKernelGGL(k_append_tail, dim3(ns + nb + nd + npb), dim3(256), 0, s, perm, sorted, M, g, V, rows, from, bmin,
+                       dir, plane, levels, stab, ns, nb, nd);
     return hipGetLastError();
 }
 
-hipError_t launch_rank_sort(const uint32_t* keys, int64_t n, int W, uint32_t* sorted, int32_t* lperm, hipStream_t s) {
-    hipLaunchKernelGGL(k_rank_sort, dim3(blocks_for(n, kRankThreads)), dim3(kRankThreads), 0, s, keys, n, W, sorted,
-                       lperm);
+hipError_t launch_rank_ub(const uint32_t* keys, int64_t n, const uint32_t* old_sorted, int64_t N, int W,
+                          uint32_t* sorted, int32_t* lperm, int64_t* ub, hipStream_t s) {
+    hipLaunchKernelGGL(k_rank_ub, dim3(blocks_for(n, kRankUbWaves)), dim3(kRankUbWaves * kWave), 0, s, keys, n,
+                       old_sorted, N, W, sorted, lperm, ub);
     return hipGetLastError();
 }
 

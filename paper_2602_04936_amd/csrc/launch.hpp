@@ -36,12 +36,15 @@ hipError_t launch_merge_sorted(const uint32_t* sorted, const int32_t* perm, cons
 // order by rank (small n)
 hipError_t launch_pack_keys(const void* tokens, int64_t n, RowGeo g, uint32_t V, uint32_t* keys, uint32_t* bad,
                             uint32_t mark, hipStream_t s);
-// after an append's merge: tie summaries and first-token directory of the
-// merged copy (M rows) and plane entries [from, plane_entries(M))
+// after an append's merge, in one launch: search tables (levels > 0), tie
+// summaries and first-token directory of the merged copy (M rows), and plane
+// entries [from, plane_entries(M))
 hipError_t launch_append_tail(const int32_t* perm, const uint32_t* sorted, int64_t M, RowGeo g, int V,
                               const uint32_t* rows, int64_t from, uint32_t* bmin, uint32_t* dir, uint64_t* plane,
-                              hipStream_t s);
-hipError_t launch_rank_sort(const uint32_t* keys, int64_t n, int W, uint32_t* sorted, int32_t* lperm, hipStream_t s);
+                              int levels, uint4* stab, hipStream_t s);
+// rank sort of n <= 8,192 new rows and their upper bounds among the N old sorted rows, one wave per new row
+hipError_t launch_rank_ub(const uint32_t* keys, int64_t n, const uint32_t* old_sorted, int64_t N, int W,
+                          uint32_t* sorted, int32_t* lperm, int64_t* ub, hipStream_t s);
 hipError_t launch_search_tables(const uint32_t* sorted, int64_t N, int W, int levels, uint4* stab,
                                 hipStream_t s);
 
