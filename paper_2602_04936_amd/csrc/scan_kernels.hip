@@ -275,10 +275,6 @@ __device__ __forceinline__ uint32_t hash_slot(uint64_t key) {
     return x & (kHashSlots - 1);
 }
 
-// Waves that share one sampled chunk in groups of TQ queries (see k_scan).
-template <int TQ>
-constexpr int seed_split() { return TQ >= 32 ? kScanWaves : 1; }
-
 template <int NR, int TQ, bool kHash>
 __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 6 : 1))) void k_scan(IndexView ix, QueryBatch qb,
                                                              const uint32_t* __restrict__ qkeys, ScanGrid sg,
@@ -286,7 +282,6 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
                                                              uint32_t* __restrict__ cnt,
                                                              uint64_t* __restrict__ gthr) {
     static_assert(TQ <= 64, "one lane and one flag bit per query");
-    constexpr int kSeedSplit = seed_split<TQ>();
     extern __shared__ uint64_t s_dyn64[];
     const RowGeo g = ix.g;
     const int W = g.W;
@@ -298,23 +293,11 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
     const unsigned xcd = b & 7u, q8 = nb >> 3, r8 = nb & 7u;
     const unsigned lb = (xcd < r8 ? xcd * (q8 + 1) : r8 * (q8 + 1) + (xcd - r8) * q8) + (b >> 3);
     const int grp = (int)(lb % (unsigned)sg.qgroups);
-    const int lbq = (int)(lb / (unsigned)sg.qgroups);  // the block's place among its group's blocks
-    // the block's parts: with kSeedSplit > 1 (large groups) each sampled
-    // chunk gets a block of its own whose waves share the chunk and split the
-    // group's queries (the sampled rows carry most of the slow-path work:
-    // their filters are looser), and every later block takes 4 main chunks;
-    // otherwise every block takes 4 consecutive parts
-    const bool seed_block = kSeedSplit > 1 && lbq < sg.seed_chunks;
-    const int pidx0 = seed_block ? lbq : kSeedSplit > 1 ? sg.seed_chunks + (lbq - sg.seed_chunks) * kScanWaves
-                                                        : lbq * kScanWaves;
-    const int pidx = seed_block ? pidx0 : pidx0 + wv;
-    const int block_parts = seed_block ? 1 : kScanWaves;
+    const int pidx0 = (int)(lb / (unsigned)sg.qgroups) * kScanWaves;
+    const int pidx = pidx0 + wv;
     const int64_t q0i = (int64_t)grp * TQ;
     const int ntq = (int)(qb.Q - q0i < TQ ? qb.Q - q0i : TQ);
-    const uint64_t share = seed_block ? (TQ / kSeedSplit >= 64 ? ~0ull : ((1ull << (TQ / kSeedSplit)) - 1))
-                                            << (wv * (TQ / kSeedSplit))
-                                      : ~0ull;  // the wave's queries
-    const uint64_t real = (ntq >= 64 ? ~0ull : (1ull << ntq) - 1) & share;
+    const uint64_t real = ntq >= 64 ? ~0ull : (1ull << ntq) - 1;
     const int64_t N = ix.N;
 
     // rows of part p: the seed chunks first (sampled rows: their looser
@@ -399,7 +382,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
                 const uint32_t* q = s_q + lane * W;
                 const uint64_t q01 = ((uint64_t)q[0] << 32) | (W > 1 ? q[1] : 0u);
                 int64_t first = N;  // the block's first row
-                for (int j = 0; j < block_parts && pidx0 + j < sg.nparts; ++j) {
+                for (int j = 0; j < kScanWaves && pidx0 + j < sg.nparts; ++j) {
                     int64_t lo, hi;
                     chunk_rows_of(pidx0 + j, lo, hi);
                     first = lo < first ? lo : first;
@@ -504,7 +487,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
             // publish the limits this wave tightened since the last time, and
             // pick up tighter ones reached by other waves: lane i reads query
             // i's limit with a plain load (a stale value only prunes less)
-            if (lane < ntq && ((share >> lane) & 1)) {
+            if (lane < ntq) {
                 const uint64_t mylim = filt[lane].lim;
                 if (mylim < published) {
                     atomicMin((unsigned long long*)(gthr + q0i + lane), (unsigned long long)mylim);
@@ -736,7 +719,7 @@ __global__ __launch_bounds__(kScanWaves * kWave) __attribute__((amdgpu_waves_per
     }
     // limits this wave tightened since it last published them go to the
     // shared ones (waves that start later read them)
-    if (lane < ntq && ((share >> lane) & 1)) {
+    if (lane < ntq) {
         const uint64_t mylim = filt[lane].lim;
         if (mylim < published) atomicMin((unsigned long long*)(gthr + q0i + lane), (unsigned long long)mylim);
     }
@@ -1005,10 +988,7 @@ static void launch_scan_t(const IndexView& ix, const QueryBatch& qb, const ScanP
     sg.qgroups = p.qgroups;
     sg.lstride = k_max;
     const size_t shm = scan_block_lds(TQ, H, k_max, ix.g.W);
-    const int64_t per_group = seed_split<TQ>() > 1
-                                  ? p.seed_chunks + ((int64_t)p.chunks + kScanWaves - 1) / kScanWaves
-                                  : ((int64_t)p.nparts + kScanWaves - 1) / kScanWaves;
-    const int64_t blocks = (int64_t)p.qgroups * per_group;
+    const int64_t blocks = (int64_t)p.qgroups * ((p.nparts + kScanWaves - 1) / kScanWaves);
     hipLaunchKernelGGL((k_scan<NR, TQ, H>), dim3((unsigned)blocks), dim3(kScanWaves * kWave), shm, s, ix, qb, sc.qkeys,
                        sg, sc.cap, sc.part, sc.cnt, sc.gthr);
 }
