@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="duration of each fixed-rate serving run (0 disables)")
     ap.add_argument("--serve-rates", type=str, default="1000,10000,100000")
+    ap.add_argument("--saturation-qps", type=float, default=1_000_000.0,
+                    help="offered load of a one-second serving burst that the synchronous scan cannot keep up with (0: skip)")
     ap.add_argument("--no-uneven", dest="uneven", action="store_false",
                     help="skip the uneven-k batch comparison")
     ap.add_argument("--sensor-steps", type=int, default=5000,
@@ -367,6 +369,19 @@ def main():
             rep.update(served_check(idx, reqs, w.db))
             serving.setdefault("index_continuous_batching_k_uniform_1_100", {})[str(int(rate))] = rep
             log(args, f"[bench] served index path, k uniform 1..100 @{int(rate)}/s: {rep}")
+
+        # where the two paths part: a one-second burst at 1,000,000 queries/s
+        # (about 87,000 requests), the synchronous scan cut off after 3 s
+        if args.saturation_qps > 0:
+            sat = {"offered_qps": args.saturation_qps, "seconds": 1.0}
+            t, b, kk = synth.serving_schedule(args.saturation_qps, 1.0, seed=1004, k_mode="fixed", k_fixed=args.k)
+            reqs = serve.requests_from_schedule(w.queries, t, b, kk)
+            sat["index_continuous_batching"] = serve.run_served(idx, reqs)
+            sat["index_continuous_batching"]["results_match_batch_run"] = served_match(reqs, ref, w.Q)
+            reqs = serve.requests_from_schedule(w.queries, t, b, kk)
+            sat["scan_synchronous"] = serve.run_synchronous(idx, reqs, scan=True, max_wall_s=3.0)
+            serving["saturation"] = sat
+            log(args, f"[bench] burst at {args.saturation_qps:.0f} queries/s: {sat}")
 
     # ---- uneven batch: the same 8,192 queries with k uniform on {1, 10, 100}:
     # one plain launch, per-k-bucket plain launches, and one persistent launch
