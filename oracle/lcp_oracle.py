@@ -21,6 +21,11 @@ Everything here is written straight from the paper's definitions, favouring
   as unsigned integers with position 0 most significant, equal rows by id.
 * Prefix buckets (section 6.2, Definition "Prefix Bucket"): the rows sharing a
   given length-d prefix, which form a contiguous range of the sorted order.
+* The bucket range scan (section 6.2, Definition "Thermal-Aware Logic";
+  Appendix D.1, TALRangeScan): a query scans only the rows of its own
+  depth-d bucket, and its answer is the top-k of those rows alone.  Reading
+  taken: rank order and ids as in the top-k definition, and (-1, -1) past the
+  bucket's size (an empty bucket gives k pads).
 
 All arithmetic is integer; results are exact.
 """
@@ -39,6 +44,8 @@ __all__ = [
     "adjacent_lcp",
     "lower_bound",
     "prefix_bucket",
+    "bucket_topk",
+    "bucket_topk_batch",
     "csr_offsets",
 ]
 
@@ -147,3 +154,39 @@ def prefix_bucket(db: np.ndarray, perm: np.ndarray, q, d: int):
         p = lower_bound(db, perm, q)
         return p, p
     return int(idx[0]), int(idx[-1]) + 1
+
+
+def bucket_topk(db: np.ndarray, q: np.ndarray, k: int, d: int):
+    """Top-k of the query's depth-d prefix bucket alone (section 6.2,
+    Definitions "Prefix Bucket" and "Thermal-Aware Logic").
+
+    The bucket is every row whose first d tokens equal q's (d = 0: every row);
+    its rows are ranked as in topk (LCP descending, id ascending, ids of the
+    whole database) and the first k returned, padded with (-1, -1).
+    """
+    if k < 1:
+        raise ValueError("k must be >= 1")
+    db = np.asarray(db)
+    q = np.asarray(q)
+    member = (db[:, :d] == q[None, :d]).all(axis=1)
+    ids = np.nonzero(member)[0].astype(np.int64)
+    v = lcp_against(db[ids], q)
+    order = np.lexsort((ids, -v.astype(np.int64)))[:k]
+    out_ids = np.full(k, -1, dtype=np.int32)
+    out_lcp = np.full(k, -1, dtype=np.int32)
+    out_ids[: order.shape[0]] = ids[order]
+    out_lcp[: order.shape[0]] = v[order]
+    return out_ids, out_lcp
+
+
+def bucket_topk_batch(db: np.ndarray, queries: np.ndarray, ks, d: int):
+    """bucket_topk for a batch; outputs concatenated in query order (CSR by k)."""
+    ks = np.broadcast_to(np.asarray(ks, dtype=np.int64), (queries.shape[0],))
+    off = csr_offsets(ks)
+    ids = np.empty(off[-1], dtype=np.int32)
+    lcps = np.empty(off[-1], dtype=np.int32)
+    for i in range(queries.shape[0]):
+        a, b = bucket_topk(db, queries[i], int(ks[i]), d)
+        ids[off[i]:off[i + 1]] = a
+        lcps[off[i]:off[i + 1]] = b
+    return ids, lcps, off

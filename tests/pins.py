@@ -18,6 +18,11 @@ Independent facts used (none re-types the oracle's arithmetic):
   from the ultrametric property (section 2.1, Theorem "Ultrametric Property")
   and sorted order, checked against brute-force pairwise LCPs; the insertion
   point checked against its counting definition.
+* The bucket range scan (section 6.2): a row is in the query's depth-d bucket
+  exactly when its LCP with the query is at least d, so the bucket's answer is
+  the level ranking cut off below level d; and whenever the k-th best LCP over
+  all rows is at least d the bucket holds every row that can rank, so its
+  answer equals the full top-k (Theorem "Range Scan Complexity").
 """
 from __future__ import annotations
 
@@ -142,3 +147,61 @@ def check_lower_bound(sorted_fn, lb_fn, db, q):
     perm = sorted_fn(db)
     want = sum(1 for r in db if tuple(int(x) for x in r) < tuple(int(x) for x in q))
     assert lb_fn(db, perm, q) == want
+
+
+def bucket_level_ranking(db, q, k, d):
+    """Second formulation of the bucket scan: levels L, L-1, ..., d of the
+    level ranking (rows below level d are outside the bucket)."""
+    L = len(q)
+    lv = [ref_lcp(r, q) for r in db]
+    ids, lcps = [], []
+    for c in range(L, d - 1, -1):
+        for i, v in enumerate(lv):
+            if v == c:
+                ids.append(i)
+                lcps.append(c)
+    ids, lcps = ids[:k], lcps[:k]
+    return ids + [-1] * (k - len(ids)), lcps + [-1] * (k - len(lcps))
+
+
+def check_bucket_exhaustive(bucket_fn, V=2, L_values=(1, 2, 3), N_max=3, k_extra=2):
+    """Every database of N <= N_max rows over Sigma^L, every query, every depth
+    0..L and every k in 1..N+k_extra."""
+    for L in L_values:
+        alphabet_rows = [np.array(r, dtype=np.uint8) for r in itertools.product(range(V), repeat=L)]
+        for N in range(1, N_max + 1):
+            for rows in itertools.product(range(len(alphabet_rows)), repeat=N):
+                db = np.stack([alphabet_rows[i] for i in rows])
+                for q in alphabet_rows:
+                    for d in range(L + 1):
+                        for k in range(1, N + k_extra + 1):
+                            ids, lcps = bucket_fn(db, q, k, d)
+                            want = bucket_level_ranking(db, q, k, d)
+                            got = (list(map(int, ids)), list(map(int, lcps)))
+                            assert got == want, (db.tolist(), q.tolist(), d, k)
+
+
+def check_bucket_golden(bucket_fn):
+    g = load_golden()
+    db = np.array(g["db"], dtype=np.uint8)
+    for case in g["bucket_scan"]:
+        q = np.array(case["q"], dtype=np.uint8)
+        ids, lcps = bucket_fn(db, q, case["k"], case["d"])
+        assert list(map(int, ids)) == case["ids"], case
+        assert list(map(int, lcps)) == case["lcps"], case
+
+
+def check_bucket_theorem(bucket_fn, topk_fn, db, q, k, d):
+    """When the k-th best LCP over all rows is >= d (and N >= k) the bucket
+    answer is the full answer; otherwise it is the full ranking's prefix of
+    rows with LCP >= d, then pads."""
+    full_ids, full_lcps = topk_fn(db, q, db.shape[0])
+    ids, lcps = bucket_fn(db, q, k, d)
+    ids, lcps = list(map(int, ids)), list(map(int, lcps))
+    keep = [(int(i), int(v)) for i, v in zip(full_ids, full_lcps) if v >= d][:k]
+    want_ids = [i for i, _ in keep] + [-1] * (k - len(keep))
+    want_lcps = [v for _, v in keep] + [-1] * (k - len(keep))
+    assert (ids, lcps) == (want_ids, want_lcps), (q.tolist(), k, d)
+    if k <= db.shape[0] and int(full_lcps[k - 1]) >= d:
+        a, b = topk_fn(db, q, k)
+        assert ids == list(map(int, a)) and lcps == list(map(int, b))

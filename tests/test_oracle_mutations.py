@@ -163,3 +163,85 @@ def test_structure_mutant_is_caught(mut):
 
 def test_unmutated_structure_passes_suite():
     assert not _structure_suite_fails(O.sorted_permutation, O.adjacent_lcp, O.lower_bound)
+
+
+# ---- bucket range scan (section 6.2)
+
+def _bucket_depth_minus_one(db, q, k, d):
+    return O.bucket_topk(db, q, k, max(d - 1, 0))
+
+
+def _bucket_depth_plus_one(db, q, k, d):
+    return O.bucket_topk(db, q, k, min(d + 1, db.shape[1]))
+
+
+def _bucket_by_last_tokens(db, q, k, d):
+    L = db.shape[1]
+    member = (db[:, L - d:] == q[None, L - d:]).all(axis=1) if d else np.ones(db.shape[0], bool)
+    ids = np.nonzero(member)[0]
+    v = O.lcp_against(db[ids], q)
+    order = np.lexsort((ids, -v.astype(np.int64)))[:k]
+    out_i = np.full(k, -1, np.int32)
+    out_l = np.full(k, -1, np.int32)
+    out_i[:len(order)] = ids[order]
+    out_l[:len(order)] = v[order]
+    return out_i, out_l
+
+
+def _bucket_ignored(db, q, k, d):
+    return O.topk(db, q, k)
+
+
+def _bucket_local_ids(db, q, k, d):
+    member = (db[:, :d] == q[None, :d]).all(axis=1)
+    sub = db[member]
+    return O.topk(sub, q, k) if sub.shape[0] else (np.full(k, -1, np.int32), np.full(k, -1, np.int32))
+
+
+def _bucket_ties_by_sorted_position(db, q, k, d):
+    perm = O.sorted_permutation(db)
+    t = db[perm]
+    member = (t[:, :d] == q[None, :d]).all(axis=1)
+    pos = np.nonzero(member)[0]
+    v = O.lcp_against(t[pos], q)
+    order = np.lexsort((pos, -v.astype(np.int64)))[:k]
+    out_i = np.full(k, -1, np.int32)
+    out_l = np.full(k, -1, np.int32)
+    out_i[:len(order)] = perm[pos[order]]
+    out_l[:len(order)] = v[order]
+    return out_i, out_l
+
+
+BUCKET_MUTANTS = {
+    "depth_minus_one": _bucket_depth_minus_one,
+    "depth_plus_one": _bucket_depth_plus_one,
+    "bucket_by_last_tokens": _bucket_by_last_tokens,
+    "bucket_ignored": _bucket_ignored,
+    "ids_local_to_bucket": _bucket_local_ids,
+    "ties_by_sorted_position": _bucket_ties_by_sorted_position,
+}
+
+
+def _bucket_pin_suite_fails(fn):
+    if _fails(pins.check_bucket_golden, fn):
+        return True
+    if _fails(pins.check_bucket_exhaustive, fn, 2, (1, 2, 3), 3):
+        return True
+    rng = np.random.default_rng(0)
+    db = synth.random_rows(rng, 60, 5, 3)
+    for _ in range(10):
+        q = db[rng.integers(0, 60)]
+        k = int(rng.integers(1, 65))
+        for d in range(6):
+            if _fails(pins.check_bucket_theorem, fn, O.topk, db, q, k, d):
+                return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(BUCKET_MUTANTS))
+def test_bucket_mutant_is_caught(name):
+    assert _bucket_pin_suite_fails(BUCKET_MUTANTS[name]), name
+
+
+def test_unmutated_bucket_passes_suite():
+    assert not _bucket_pin_suite_fails(O.bucket_topk)

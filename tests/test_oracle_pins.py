@@ -93,6 +93,36 @@ def test_prefix_bucket_matches_definition():
                 assert lo == hi
 
 
+def test_bucket_scan_golden_handworked():
+    """Hand-derived bucket answers and bounds (section 6.2, Appendix D.1)."""
+    pins.check_bucket_golden(O.bucket_topk)
+    g = pins.load_golden()
+    db = np.array(g["db"], dtype=np.uint8)
+    perm = O.sorted_permutation(db)
+    for case in g["bucket_scan"]:
+        assert list(O.prefix_bucket(db, perm, np.array(case["q"]), case["d"])) == case["bounds"], case
+
+
+def test_bucket_scan_exhaustive_tiny():
+    pins.check_bucket_exhaustive(O.bucket_topk, V=2, L_values=(1, 2, 3), N_max=3)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bucket_scan_reduces_to_full_answer(seed):
+    """Theorem "Range Scan Complexity": the bucket holds every row that can rank
+    once the k-th best LCP reaches d; d = 0 is the full scan."""
+    rng = np.random.default_rng(100 + seed)
+    db = synth.random_rows(rng, 120, 6, 3)
+    for _ in range(12):
+        q = db[rng.integers(0, 120)].copy() if rng.random() < 0.5 else synth.random_rows(rng, 1, 6, 3)[0]
+        k = int(rng.integers(1, 130))
+        for d in range(7):
+            pins.check_bucket_theorem(O.bucket_topk, O.topk, db, q, k, d)
+        a, b = O.bucket_topk(db, q, k, 0)
+        c, e = O.topk(db, q, k)
+        assert (a == c).all() and (b == e).all()
+
+
 def test_c_oracle_matches_numpy_oracle_c1():
     w = synth.c1_tiny()
     ids, lcps, off = oracle.c_topk(w.db, w.queries, w.k)
