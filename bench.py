@@ -508,15 +508,14 @@ def main():
         log(args, f"[bench] uneven batch: {uneven}")
 
     # ---- energy per query from the socket energy accumulator: idle draw, the
-    # index path, the full scan, and full scans over the first N/B rows (the
-    # bucket-count sweep: a query confined to one of B equal prefix buckets
-    # scans N/B rows)
+    # index path, the full scan, and the bucket range scan at B = 1, 16, 256
+    # prefix buckets (each query scans only its own bucket)
     energy = None
     if args.energy_seconds > 0:
         from paper_2602_04936_amd import energy as E
         meter, why = E.try_meter(dev)
         if meter is None:
-            energy = {"unavailable": why}
+            energy = {"unavailable": why, "prefix_bucket_scan": prefix_bucket_sweep(P, idx, q_dev, args.k)}
         else:
             es = args.energy_seconds
             iw = meter.idle_watts(es)
@@ -535,7 +534,7 @@ def main():
 
             energy["index"] = meter.measure(run_index, es, sync_every=64)
             energy["full_scan"] = meter.measure(run_scan(idx), es, sync_every=1)
-            energy["prefix_bucket_scan"] = prefix_bucket_sweep(P, w, args.k, dev, meter, es, idle=iw)
+            energy["prefix_bucket_scan"] = prefix_bucket_sweep(P, idx, q_dev, args.k, meter, es, idle=iw)
             ji, js = energy["index"].get("j_per_query"), energy["full_scan"].get("j_per_query")
             energy["index_vs_full_scan_energy_ratio"] = round(js / ji, 1) if ji and js else None
             meter.close()
@@ -719,60 +718,47 @@ def work_shape(st, N, k, row_bytes, probes):
     }
 
 
-def prefix_bucket_sweep(P, w, k, dev, meter, seconds, idle=None):
-    """Full scans confined to prefix buckets (the bucketed range scan of the
-    paper's energy theorem): at depth d the rows are split by their first d
-    tokens (c3's hierarchy gives 16^d buckets), one index per bucket, and each
-    query scans only the bucket of its own first d tokens.  J/query and the
-    mean rows scanned per query, for d = 0, 1, 2 (B = 1, 16, 256).  A query
-    whose prefix no row has scans nothing.  Besides J/query (board power over
-    the query rate), the share above the idle draw is given: at small buckets
-    the calls are short and the idle draw dominates."""
+def prefix_bucket_sweep(P, idx, q_dev, k, meter=None, seconds=0.0, idle=None):
+    """The bucket range scan of section 6.2 (lcp_bucket_scan_topk) over the
+    whole batch, one call per depth d = 0, 1, 2: each query scans only the
+    sorted rows that share its first d tokens (c3's 16-ary hierarchy gives
+    B = 1, 16, 256 buckets).  Per depth: the GPU time of one call (events),
+    the mean rows scanned per query and the queries whose bucket is empty
+    (from the call's bucket bounds), and with a meter J/query, the share above
+    the idle draw and the query rate under the meter."""
     import torch
+    Q = int(q_dev.shape[0])
+    o = (torch.empty(Q * k, dtype=torch.int32, device=q_dev.device),
+         torch.empty(Q * k, dtype=torch.int32, device=q_dev.device))
     out = {}
     for d in (0, 1, 2):
-        if d == 0:
-            groups = {(): (np.arange(w.N), np.arange(w.Q))}
-        else:
-            dk = np.ascontiguousarray(w.db[:, :d]).view(np.dtype((np.void, 2 * d))).ravel()
-            qk = np.ascontiguousarray(w.queries[:, :d]).view(np.dtype((np.void, 2 * d))).ravel()
-            keys, inv = np.unique(dk, return_inverse=True)
-            order = np.argsort(inv, kind="stable")
-            starts = np.searchsorted(inv[order], np.arange(len(keys) + 1))
-            qpos = np.searchsorted(keys, qk)
-            qhit = (qpos < len(keys)) & (keys[np.minimum(qpos, len(keys) - 1)] == qk)
-            groups = {}
-            for b in range(len(keys)):
-                qsel = np.nonzero(qhit & (qpos == b))[0]
-                if len(qsel):
-                    groups[b] = (order[starts[b]:starts[b + 1]], qsel)
-        subs = []
-        for rows, qsel in groups.values():
-            sub = P.Index(P.to_device_tokens(w.db[rows], dev), w.V)
-            q = P.to_device_tokens(w.queries[qsel], dev)
-            o = (torch.empty(len(qsel) * k, dtype=torch.int32, device=dev),
-                 torch.empty(len(qsel) * k, dtype=torch.int32, device=dev))
-            subs.append((sub, q, o, len(rows)))
-        nq = sum(x[1].shape[0] for x in subs)
-        scanned = sum(x[1].shape[0] * x[3] for x in subs) / max(nq, 1)
-
-        def run():
-            for sub, q, o, _ in subs:
-                sub.scan_topk(q, k, out=o)
-            return nq
-
-        rep = meter.measure(run, seconds, sync_every=1)
-        above = None
-        if idle is not None and rep.get("watts") and rep.get("queries_per_s"):
-            above = (rep["watts"] - idle) / rep["queries_per_s"]
-        out[str(len(groups) if d else 1)] = {"depth": d, "buckets_with_queries": len(groups), "queries": int(nq),
-                                              "mean_rows_scanned": round(float(scanned), 1),
-                                              "j_per_query": rep.get("j_per_query"),
-                                              "j_per_query_above_idle": above, "watts": rep.get("watts"),
-                                              "queries_per_s": rep.get("queries_per_s")}
-        for sub, _, _, _ in subs:
-            sub.close()
+        _, b = idx.bucket_scan_topk(q_dev, k, d, out=o, bounds=True)  # the first call lays out the sorted prefixes
         torch.cuda.synchronize()
+        rows = (b[:, 1] - b[:, 0]).to(torch.float64)
+        buckets = int(torch.unique(b[rows > 0, 0]).numel())
+        reps = 4 if d == 0 else 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            idx.bucket_scan_topk(q_dev, k, d, out=o)
+        e1.record()
+        torch.cuda.synchronize()
+        gpu_ms = e0.elapsed_time(e1) / reps
+        rec = {"depth": d, "buckets_with_queries": buckets, "queries": Q,
+               "mean_rows_scanned": round(float(rows.mean()), 1), "empty_bucket_queries": int((rows == 0).sum()),
+               "gpu_ms_per_batch": round(gpu_ms, 4), "gpu_qps": round(Q / (gpu_ms * 1e-3), 1)}
+        if meter is not None:
+            def run():
+                idx.bucket_scan_topk(q_dev, k, d, out=o)
+                return Q
+
+            rep = meter.measure(run, seconds, sync_every=8)
+            above = None
+            if idle is not None and rep.get("watts") and rep.get("queries_per_s"):
+                above = (rep["watts"] - idle) / rep["queries_per_s"]
+            rec.update({"j_per_query": rep.get("j_per_query"), "j_per_query_above_idle": above,
+                        "watts": rep.get("watts"), "queries_per_s": rep.get("queries_per_s")})
+        out[str(16 ** d)] = rec
     return out
 
 

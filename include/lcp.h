@@ -136,6 +136,33 @@ lcp_status lcp_scan_topk(const lcp_index* index, const void* queries, int64_t Q,
                          int32_t* out_ids, int32_t* out_lcp, void* stream);
 
 /*
+ * Prefix-bucket range scan (section 6.2: Definition "Prefix Bucket", Theorem
+ * "Range Scan Complexity", Definition "Thermal-Aware Logic"; the range scan of
+ * Appendix D.1).  Query i scans only its bucket: the rows whose first `depth`
+ * tokens equal its own, a contiguous range of the sorted order.  Its answer is
+ * the top-k of that bucket alone, by the section 2.1 order (LCP descending,
+ * id ascending), with LCP and ids as in lcp_topk; when the bucket holds fewer
+ * than k[i] rows (none, if no row has the query's prefix) the remaining
+ * entries are -1.  Whenever the k-th best LCP over all rows is at least
+ * `depth`, the answer equals lcp_topk's.
+ *
+ *   depth  : 0 <= depth <= L; 0 makes the bucket every row (a full scan).
+ *   bounds : NULL, or device int32 [Q][2], 8-byte aligned: receives each
+ *            query's bucket as sorted positions [lo, hi) (positions of the
+ *            sorted order that lcp_index_views exposes); lo == hi for an
+ *            empty bucket, at the query's insertion point.
+ * Other arguments, the output layout and k's range are those of lcp_topk.
+ * The first call after a build, append or reserve also lays out the 8-byte
+ * prefixes of the sorted rows (8 bytes a row, held by the index) and waits
+ * for the device once.
+ * Errors: those of lcp_topk; LCP_EINVAL for depth outside [0, L] or a
+ * misaligned bounds.
+ */
+lcp_status lcp_bucket_scan_topk(const lcp_index* index, const void* queries, int64_t Q, int32_t depth,
+                                const int32_t* k, int32_t* out_ids, int32_t* out_lcp, int32_t* bounds,
+                                void* stream);
+
+/*
  * Device-side variants for callers that keep k and the output offsets on the
  * device (serving loops, captured graphs): no host staging, no host sync.
  *

@@ -43,6 +43,7 @@ def _load_lib() -> ctypes.CDLL:
         "lcp_index_build": [vp, i64, i32, i32, vp, ctypes.POINTER(vp)],
         "lcp_topk": [vp, vp, i64, vp, vp, vp, vp],
         "lcp_scan_topk": [vp, vp, i64, vp, vp, vp, vp],
+        "lcp_bucket_scan_topk": [vp, vp, i64, i32, vp, vp, vp, vp, vp],
         "lcp_topk_stats": [vp, vp, i64, vp, vp, vp, vp, vp],
         "lcp_topk_dev": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
         "lcp_scan_topk_dev": [vp, vp, i64, vp, vp, i32, vp, vp, vp],
@@ -205,6 +206,26 @@ class Index:
     def scan_topk(self, queries, k: Union[int, Sequence[int], np.ndarray], stream=None, out=None) -> TopK:
         """Plain full-scan path (lcp_scan_topk)."""
         return self._run(lib.lcp_scan_topk, queries, k, stream, out)
+
+    def bucket_scan_topk(self, queries, k: Union[int, Sequence[int], np.ndarray], depth: int, stream=None,
+                         out=None, bounds: bool = False):
+        """Prefix-bucket range scan (lcp_bucket_scan_topk): each query scans only the rows that share
+        its first `depth` tokens.  With bounds=True returns (TopK, bounds), bounds an int32 [Q, 2]
+        device tensor of each query's bucket [lo, hi) in sorted positions."""
+        q, kk, off = self._prep(queries, k)
+        total = int(off[-1])
+        if out is None:
+            ids = torch.empty(total, dtype=torch.int32, device=self.device)
+            lcps = torch.empty(total, dtype=torch.int32, device=self.device)
+        else:
+            ids, lcps = out
+            if ids.numel() < total or lcps.numel() < total:
+                raise ValueError("output tensors are too small")
+        b = torch.empty((q.shape[0], 2), dtype=torch.int32, device=self.device) if bounds else None
+        _check(lib.lcp_bucket_scan_topk(self._h, q.data_ptr(), q.shape[0], int(depth), kk.ctypes.data,
+                                        ids.data_ptr(), lcps.data_ptr(), b.data_ptr() if b is not None else None,
+                                        _stream_handle(stream)))
+        return (TopK(ids, lcps, off), b) if bounds else TopK(ids, lcps, off)
 
     def topk_dev(self, queries: torch.Tensor, k_dev: torch.Tensor, off_dev: torch.Tensor, k_max: int,
                  out_ids: torch.Tensor, out_lcp: torch.Tensor, stream=None, scan: bool = False,

@@ -123,6 +123,11 @@ struct lcp_index {
     int search_mode = 0;           // 0: 65-ary search tables, 1: first-token directory
     uint64_t generation = 0;       // changes of what queries read: appends, search-mode switches
     AppendScratch app;
+    // The bucket scan's sorted prefix plane (first two key words of every
+    // sorted row), built by its first call after each change of generation.
+    mutable uint64_t* d_splane = nullptr;
+    mutable int64_t splane_cap = 0;
+    mutable uint64_t splane_gen = ~0ull;
 
     mutable std::mutex mu;
     mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
@@ -264,20 +269,44 @@ lcp_status check_query_args(const lcp_index* idx, const void* queries, int64_t Q
     return LCP_OK;
 }
 
-enum class Path { Index, Scan };
+enum class Path { Index, Scan, Bucket };
 
 // Queries per launch: the index kernel's grid is Q/4 blocks; the scan's grid y
 // is Q/(4*tq) <= 65535 query groups.
 constexpr int64_t kSliceIndex = 1 << 20;
 constexpr int64_t kSliceScan = 65535 * 4;
 
+// The bucket scan's sorted prefix plane for the current generation; the
+// first call after a change builds it and waits for it, so that calls on
+// other streams find it complete.  Caller holds idx->mu.
+lcp_status ensure_sorted_plane(const lcp_index* idx, hipStream_t s) {
+    if (idx->splane_gen == idx->generation) return LCP_OK;
+    HIP_TRY(hipDeviceSynchronize());  // calls on other streams may still read the old plane
+    const int64_t need = plane_entries(idx->N);
+    if (need > idx->splane_cap) {
+        if (idx->d_splane) hipFree(idx->d_splane);
+        idx->d_splane = nullptr;
+        idx->splane_cap = 0;
+        HIP_TRY(hipMalloc(&idx->d_splane, (size_t)need * sizeof(uint64_t)));
+        idx->splane_cap = need;
+    }
+    HIP_TRY(launch_prefix_plane(idx->cp[idx->cur].sorted, 0, idx->N, idx->g.W, idx->d_splane, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    idx->splane_gen = idx->generation;
+    return LCP_OK;
+}
+
 lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
                    const int64_t* off_dev, int32_t k_uniform, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
-                   hipStream_t s, StreamCtx* c, int32_t* stats = nullptr) {
+                   hipStream_t s, StreamCtx* c, int32_t* stats = nullptr, int32_t depth = 0) {
     HIP_TRY(hipSetDevice(idx->device));
     const IndexView ix = idx->view();
     const size_t row_bytes = (size_t)idx->L * idx->g.tb;
-    const int64_t slice = path == Path::Index ? kSliceIndex : kSliceScan;
+    const int64_t slice = path == Path::Scan ? kSliceScan : kSliceIndex;
+    if (path == Path::Bucket) {
+        lcp_status st = ensure_sorted_plane(idx, s);
+        if (st != LCP_OK) return st;
+    }
     for (int64_t q0 = 0; q0 < Q; q0 += slice) {
         QueryBatch qb;
         qb.raw = static_cast<const uint8_t*>(queries) + (size_t)q0 * row_bytes;
@@ -289,13 +318,16 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
         qb.k_max = k_max;
         qb.out_ids = out_ids;  // offsets are absolute
         qb.out_lcp = out_lcp;
-        qb.stats = stats ? stats + 4 * q0 : nullptr;
+        qb.stats = stats && path == Path::Index ? stats + 4 * q0 : nullptr;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        if (idx->timing) {
+        if (idx->timing && path != Path::Bucket) {
             int need = path == Path::Index ? 2 : 3;
             for (int i = 0; i < need; ++i) ev[i] = take_event(idx);
         }
-        if (path == Path::Index) {
+        if (path == Path::Bucket) {
+            // the bucket bounds travel in `stats` as [Q][2]
+            HIP_TRY(launch_bucket_scan(ix, idx->d_splane, qb, depth, stats ? stats + 2 * q0 : nullptr, s));
+        } else if (path == Path::Index) {
             if (ev[0]) HIP_TRY(hipEventRecord(ev[0], s));
             HIP_TRY(launch_index_query(ix, qb, s));
             if (ev[1]) {
@@ -318,7 +350,8 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
 }
 
 lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k,
-                      int32_t* out_ids, int32_t* out_lcp, void* stream, int32_t* stats = nullptr) {
+                      int32_t* out_ids, int32_t* out_lcp, void* stream, int32_t* stats = nullptr,
+                      int32_t depth = 0) {
     lcp_status st = check_query_args(idx, queries, Q, out_ids, out_lcp);
     if (st != LCP_OK) return st;
     if (Q == 0) return LCP_OK;
@@ -344,10 +377,11 @@ lcp_status query_host(const lcp_index* idx, Path path, const void* queries, int6
                 return fail(LCP_EINVAL, "k[%lld] = %d is outside [1, %d]", (long long)i, k[i], LCP_K_MAX);
     }
     if (diff == 0)  // one k for all: offsets are i * k, nothing to copy
-        return run_dev(idx, path, queries, Q, nullptr, nullptr, k[0], kmax, out_ids, out_lcp, s, c, stats);
+        return run_dev(idx, path, queries, Q, nullptr, nullptr, k[0], kmax, out_ids, out_lcp, s, c, stats, depth);
     st = stage_k(c, Q, k);
     if (st != LCP_OK) return st;
-    return run_dev(idx, path, queries, Q, kbuf_k(c, Q), kbuf_off(c), 0, kmax, out_ids, out_lcp, s, c, stats);
+    return run_dev(idx, path, queries, Q, kbuf_k(c, Q), kbuf_off(c), 0, kmax, out_ids, out_lcp, s, c, stats,
+                   depth);
 }
 
 // Fixed scratch of the allocation-free full scan: one copy per device,
@@ -423,6 +457,7 @@ void destroy_index(lcp_index* idx) {
     for (auto e : idx->event_pool) hipEventDestroy(e);
     if (idx->d_rows) hipFree(idx->d_rows);
     if (idx->d_plane) hipFree(idx->d_plane);
+    if (idx->d_splane) hipFree(idx->d_splane);
     idx->cp[0].release();
     idx->cp[1].release();
     idx->app.release();
@@ -815,6 +850,15 @@ lcp_status lcp_topk_stats(const lcp_index* index, const void* queries, int64_t Q
 lcp_status lcp_scan_topk(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k,
                          int32_t* out_ids, int32_t* out_lcp, void* stream) {
     return query_host(index, Path::Scan, queries, Q, k, out_ids, out_lcp, stream);
+}
+
+lcp_status lcp_bucket_scan_topk(const lcp_index* index, const void* queries, int64_t Q, int32_t depth,
+                                const int32_t* k, int32_t* out_ids, int32_t* out_lcp, int32_t* bounds,
+                                void* stream) {
+    if (index && (depth < 0 || depth > index->L))
+        return fail(LCP_EINVAL, "depth = %d is outside [0, L = %d]", depth, index->L);
+    if (reinterpret_cast<uintptr_t>(bounds) % 8 != 0) return fail(LCP_EINVAL, "bounds is not 8-byte aligned");
+    return query_host(index, Path::Bucket, queries, Q, k, out_ids, out_lcp, stream, bounds, depth);
 }
 
 lcp_status lcp_topk_dev(const lcp_index* index, const void* queries, int64_t Q, const int32_t* k_dev,

@@ -1,0 +1,154 @@
+// Prefix-bucket range scan (section 6.2: Definition "Prefix Bucket",
+// Theorem "Range Scan Complexity", Definition "Thermal-Aware Logic"; the range
+// scan of Appendix D.1).
+//
+// Each query finds the range of sorted positions whose rows share its first d
+// tokens (a prefix bucket is contiguous in the sorted order) and scans only
+// that range: the LCP of every row in it, and the k best rows by (LCP
+// descending, id ascending).  One wave per query.  The rows are streamed from
+// the sorted prefix plane (the first two key words of each sorted row, 8 bytes
+// a row, coalesced), so a bucket of n rows costs about 8n bytes; the full row
+// is read only where the first two words equal the query's, and the row's id
+// only where the row can still enter the answer.
+#include "device.hpp"
+#include "launch.hpp"
+
+namespace lcpx {
+
+namespace {
+
+constexpr int kBucketWaves = 4;     // waves (queries) per block
+constexpr int kBucketUnroll = 4;    // plane loads in flight per lane
+constexpr int kBucketMaxW = (255 * 2 + 3) / 4;  // key words of the longest row: 255 two-byte tokens
+
+// Order of the first d tokens of a row against the query's: nw whole key words,
+// then the top bits `mask` of word nw (mask == 0: none).
+__device__ __forceinline__ int cmp_prefix(const uint32_t* __restrict__ row, const uint32_t* q, int nw, uint32_t mask) {
+    for (int w = 0; w < nw; ++w) {
+        const uint32_t r = row[w], t = q[w];
+        if (r != t) return r < t ? -1 : 1;
+    }
+    if (mask) {
+        const uint32_t r = row[nw] & mask, t = q[nw] & mask;
+        if (r != t) return r < t ? -1 : 1;
+    }
+    return 0;
+}
+
+// First sorted position p in [a, b) whose row's d-prefix is >= the query's
+// (upper == false) or > it (upper == true); b when there is none.  64-ary:
+// each step probes the last position of 64 equal segments, one per lane, and
+// keeps the segment where the predicate turns.
+__device__ __forceinline__ int64_t bucket_bound(const uint32_t* __restrict__ sorted, int W, const uint32_t* q, int nw,
+                                                uint32_t mask, int64_t a, int64_t b, bool upper) {
+    const int lane = lane_id();
+    while (a < b) {
+        const int64_t s = (b - a + kWave - 1) / kWave;
+        const int64_t p = a + (int64_t)(lane + 1) * s - 1;
+        const bool valid = p < b;
+        const int c = valid ? cmp_prefix(sorted + p * W, q, nw, mask) : 1;
+        const bool before = valid && (upper ? c <= 0 : c < 0);
+        const int64_t cnt = popc64(ballot(before));
+        const int64_t na = a + cnt * s;
+        const int64_t nb = a + (cnt + 1) * s - 1;
+        a = na;
+        b = nb < b ? nb : b;
+    }
+    return a;
+}
+
+template <int NR>
+__global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView ix, const uint64_t* __restrict__ splane,
+                                                                      QueryBatch qb, int depth,
+                                                                      int32_t* __restrict__ bounds) {
+    __shared__ uint32_t s_q[kBucketWaves][kBucketMaxW];
+    const RowGeo g = ix.g;
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t qi = (int64_t)blockIdx.x * kBucketWaves + wv;
+    if (qi >= qb.Q) return;  // whole waves: every wave only uses its own LDS row
+    uint32_t* q = s_q[wv];
+    for (int w = lane; w < g.W; w += kWave) q[w] = key_word(qb.raw, qi * g.L, g, w);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // ---- 1. the bucket: sorted positions [lo, hi) of the rows sharing q's first `depth` tokens
+    int64_t lo = 0, hi = ix.N;
+    if (depth > 0) {
+        const int nw = depth >> g.tpw_log2;
+        const int rem = depth & ((1 << g.tpw_log2) - 1);
+        const uint32_t mask = rem ? ~0u << (32 - (rem << g.bits_log2)) : 0u;
+        lo = bucket_bound(ix.sorted, g.W, q, nw, mask, 0, ix.N, false);
+        hi = bucket_bound(ix.sorted, g.W, q, nw, mask, lo, ix.N, true);
+    }
+    if (bounds && lane == 0) {
+        bounds[2 * qi] = (int32_t)lo;
+        bounds[2 * qi + 1] = (int32_t)hi;
+    }
+
+    // ---- 2. scan it: LCP of every row, the k best keys kept in a wave list
+    const int k = query_k(qb, qi);
+    const uint64_t qp = ((uint64_t)q[0] << 32) | (g.W > 1 ? q[1] : 0u);
+    WaveList<NR> list;
+    list.init();
+    uint64_t thr = kKeyMax;  // the k-th smallest key so far
+    for (int64_t base = lo; base < hi; base += kBucketUnroll * kWave) {
+        uint64_t pv[kBucketUnroll];
+#pragma unroll
+        for (int u = 0; u < kBucketUnroll; ++u) {
+            const int64_t p = base + u * kWave + lane;
+            pv[u] = splane[p < hi ? p : hi - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kBucketUnroll; ++u) {
+            const int64_t p = base + u * kWave + lane;
+            const bool act = p < hi;
+            const uint64_t x = pv[u] ^ qp;
+            int lcp = x ? (int)(__clzll((long long)x) >> g.bits_log2) : g.L;
+            if (act && x == 0 && g.W > 2) lcp = lcp_tail(ix.sorted + p * g.W, q, g, 2);
+            // a row enters only with an LCP of at least the k-th key's (its id decides a tie)
+            const int tl = thr == kKeyMax ? -1 : key_lcp(thr);
+            const bool cand = act && lcp >= tl;
+            if (ballot(cand)) {
+                const uint32_t id = cand ? (uint32_t)ix.perm[p] : 0u;
+                list.offer(rank_key(lcp, id), cand, k);
+                thr = list.get(k - 1);
+            }
+        }
+    }
+
+    // ---- 3. emit in rank order; entries past the bucket's size are (-1, -1)
+    const int64_t out0 = query_off(qb, qi);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int e = r * kWave + lane;
+        if (e < k) {
+            const uint64_t key = list.v[r];
+            qb.out_ids[out0 + e] = key == kKeyMax ? -1 : key_id(key);
+            qb.out_lcp[out0 + e] = key == kKeyMax ? -1 : key_lcp(key);
+        }
+    }
+}
+
+template <int NR>
+hipError_t launch_bucket_t(const IndexView& ix, const uint64_t* splane, const QueryBatch& qb, int depth,
+                           int32_t* bounds, hipStream_t s) {
+    const int64_t blocks = (qb.Q + kBucketWaves - 1) / kBucketWaves;
+    hipLaunchKernelGGL(k_bucket_scan<NR>, dim3((unsigned)blocks), dim3(kBucketWaves * kWave), 0, s, ix, splane, qb,
+                       depth, bounds);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bucket_scan(const IndexView& ix, const uint64_t* splane, const QueryBatch& qb, int depth,
+                              int32_t* bounds, hipStream_t s) {
+    if (qb.Q <= 0) return hipSuccess;
+    if (qb.k_max <= 64) return launch_bucket_t<1>(ix, splane, qb, depth, bounds, s);
+    if (qb.k_max <= 128) return launch_bucket_t<2>(ix, splane, qb, depth, bounds, s);
+    if (qb.k_max <= 256) return launch_bucket_t<4>(ix, splane, qb, depth, bounds, s);
+    return launch_bucket_t<16>(ix, splane, qb, depth, bounds, s);
+}
+
+}  // namespace lcpx

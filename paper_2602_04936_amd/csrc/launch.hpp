@@ -170,4 +170,11 @@ size_t scan_partial_entries(const ScanPlan& p, int64_t Q, int32_t k_max, const R
 hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan& p, uint64_t* scratch, hipStream_t s,
                        hipEvent_t ev_scan0, hipEvent_t ev_scan1, hipEvent_t ev_merge1);
 
+// Prefix-bucket range scan: one wave per query scans the sorted rows sharing
+// its first `depth` tokens.  splane: the first two key words of every sorted
+// row (launch_prefix_plane over the sorted copy).  bounds: null, or [Q][2]
+// int32 receiving each query's bucket [lo, hi) in sorted positions.
+hipError_t launch_bucket_scan(const IndexView& ix, const uint64_t* splane, const QueryBatch& qb, int depth,
+                              int32_t* bounds, hipStream_t s);
+
 }  // namespace lcpx
