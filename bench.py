@@ -191,6 +191,10 @@ def main():
     log(args, f"[bench] full scan: {sdt * 1e3 / args.scan_steps:.3f} ms/batch, {scan_qps / 1e6:.3f} M queries/s, "
               f"paths agree: {paths_agree}")
 
+    # ---- the bucket range scan on the same batch at B = 1, 16, 256 prefix buckets
+    bucket_scan = prefix_bucket_sweep(P, idx, q_dev, args.k)
+    log(args, f"[bench] bucket range scan: {bucket_scan}")
+
     # ---- scan bandwidth at a bandwidth-bound tile (few queries per pass)
     nbw = args.scan_bw_queries
     qbw = q_dev[:nbw]
@@ -515,7 +519,7 @@ def main():
         from paper_2602_04936_amd import energy as E
         meter, why = E.try_meter(dev)
         if meter is None:
-            energy = {"unavailable": why, "prefix_bucket_scan": prefix_bucket_sweep(P, idx, q_dev, args.k)}
+            energy = {"unavailable": why}
         else:
             es = args.energy_seconds
             iw = meter.idle_watts(es)
@@ -650,6 +654,7 @@ def main():
                           "cold_after_write_flush_us": round(cold_w_us, 2),
                           "streaming_reference_torch_sum": stream_reference(w.N * plane_bytes)},
         "large_db": large,
+        "bucket_scan": bucket_scan,
         "build_ms": round(build_ms, 2),
         "serving": serving,
         "uneven_batch": uneven,

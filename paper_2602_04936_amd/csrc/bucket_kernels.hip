@@ -18,7 +18,7 @@ namespace lcpx {
 namespace {
 
 constexpr int kBucketWaves = 4;     // waves (queries) per block
-constexpr int kBucketUnroll = 4;    // plane loads in flight per lane
+constexpr int kBucketUnroll = 2;    // 16-byte plane loads per lane and step
 constexpr int kBucketMaxW = (255 * 2 + 3) / 4;  // key words of the longest row: 255 two-byte tokens
 
 // Order of the first d tokens of a row against the query's: nw whole key words,
@@ -87,35 +87,69 @@ __global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView 
         bounds[2 * qi + 1] = (int32_t)hi;
     }
 
-    // ---- 2. scan it: LCP of every row, the k best keys kept in a wave list
+    // ---- 2. scan it: LCP of every row, the k best keys kept in a wave list.
+    // Each lane takes two adjacent rows per 16-byte load; a step is
+    // kBucketUnroll loads per lane, and the next step's loads are issued
+    // before this step's rows are compared.  The range is widened to whole
+    // pairs ([lo & ~1, (hi + 1) & ~1) lies inside the plane, whose entry count
+    // is even); rows outside [lo, hi) are masked.
     const int k = query_k(qb, qi);
     const uint64_t qp = ((uint64_t)q[0] << 32) | (g.W > 1 ? q[1] : 0u);
     WaveList<NR> list;
     list.init();
     uint64_t thr = kKeyMax;  // the k-th smallest key so far
-    for (int64_t base = lo; base < hi; base += kBucketUnroll * kWave) {
-        uint64_t pv[kBucketUnroll];
+    const int64_t a0 = lo & ~(int64_t)1;
+    const int64_t hend = (hi + 1) & ~(int64_t)1;
+    constexpr int kStep = kBucketUnroll * 2 * kWave;
+    auto load_pair = [&](int64_t b, int u) -> uint4 {
+        int64_t p = b + u * 2 * kWave + 2 * lane;
+        p = p < hend ? p : hend - 2;
+        return *reinterpret_cast<const uint4*>(splane + p);
+    };
+    auto row_lcp = [&](uint64_t v, int64_t p) -> int {
+        const uint64_t x = v ^ qp;
+        int lcp = x ? (int)(__clzll((long long)x) >> g.bits_log2) : g.L;
+        if (x == 0 && g.W > 2 && p < hi) lcp = lcp_tail(ix.sorted + p * g.W, q, g, 2);
+        return lcp;
+    };
+    auto scan_step = [&](const uint4 (&buf)[kBucketUnroll], int64_t base) {
 #pragma unroll
         for (int u = 0; u < kBucketUnroll; ++u) {
-            const int64_t p = base + u * kWave + lane;
-            pv[u] = splane[p < hi ? p : hi - 1];
-        }
-#pragma unroll
-        for (int u = 0; u < kBucketUnroll; ++u) {
-            const int64_t p = base + u * kWave + lane;
-            const bool act = p < hi;
-            const uint64_t x = pv[u] ^ qp;
-            int lcp = x ? (int)(__clzll((long long)x) >> g.bits_log2) : g.L;
-            if (act && x == 0 && g.W > 2) lcp = lcp_tail(ix.sorted + p * g.W, q, g, 2);
+            const int64_t p0 = base + u * 2 * kWave + 2 * lane;
+            const bool act0 = p0 >= lo && p0 < hi;
+            const bool act1 = p0 + 1 >= lo && p0 + 1 < hi;
+            const int lcp0 = row_lcp(((uint64_t)buf[u].y << 32) | buf[u].x, p0);
+            const int lcp1 = row_lcp(((uint64_t)buf[u].w << 32) | buf[u].z, p0 + 1);
             // a row enters only with an LCP of at least the k-th key's (its id decides a tie)
             const int tl = thr == kKeyMax ? -1 : key_lcp(thr);
-            const bool cand = act && lcp >= tl;
-            if (ballot(cand)) {
-                const uint32_t id = cand ? (uint32_t)ix.perm[p] : 0u;
-                list.offer(rank_key(lcp, id), cand, k);
+            const bool c0 = act0 && lcp0 >= tl;
+            const bool c1 = act1 && lcp1 >= tl;
+            if (ballot(c0 || c1)) {
+                const uint32_t id0 = c0 ? (uint32_t)ix.perm[p0] : 0u;
+                const uint32_t id1 = c1 ? (uint32_t)ix.perm[p0 + 1] : 0u;
+                list.offer(rank_key(lcp0, id0), c0, k);
+                list.offer(rank_key(lcp1, id1), c1, k);
                 thr = list.get(k - 1);
             }
         }
+    };
+    // two register sets in turn: one step's loads are in flight while the
+    // other's rows are compared, with no copy between them
+    uint4 ba[kBucketUnroll], bb[kBucketUnroll];
+    if (lo < hi) {
+#pragma unroll
+        for (int u = 0; u < kBucketUnroll; ++u) ba[u] = load_pair(a0, u);
+    }
+    for (int64_t base = a0; base < hi;) {
+#pragma unroll
+        for (int u = 0; u < kBucketUnroll; ++u) bb[u] = load_pair(base + kStep, u);
+        scan_step(ba, base);
+        base += kStep;
+        if (base >= hi) break;
+#pragma unroll
+        for (int u = 0; u < kBucketUnroll; ++u) ba[u] = load_pair(base + kStep, u);
+        scan_step(bb, base);
+        base += kStep;
     }
 
     // ---- 3. emit in rank order; entries past the bucket's size are (-1, -1)
