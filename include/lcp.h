@@ -152,9 +152,10 @@ lcp_status lcp_scan_topk(const lcp_index* index, const void* queries, int64_t Q,
  *            sorted order that lcp_index_views exposes); lo == hi for an
  *            empty bucket, at the query's insertion point.
  * Other arguments, the output layout and k's range are those of lcp_topk.
- * The first call after a build, append or reserve also lays out the 8-byte
- * prefixes of the sorted rows (8 bytes a row, held by the index) and waits
- * for the device once.
+ * The first call at a given depth after a build, append or reserve also lays
+ * out what that depth streams (the first two key words of the sorted rows, or
+ * one key word of them once depth covers whole words: 8 or 4 bytes a row, held
+ * by the index) and waits for the device once.
  * Errors: those of lcp_topk; LCP_EINVAL for depth outside [0, L] or a
  * misaligned bounds.
  */

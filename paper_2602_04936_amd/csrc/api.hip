@@ -123,11 +123,14 @@ struct lcp_index {
     int search_mode = 0;           // 0: 65-ary search tables, 1: first-token directory
     uint64_t generation = 0;       // changes of what queries read: appends, search-mode switches
     AppendScratch app;
-    // The bucket scan's sorted prefix plane (first two key words of every
-    // sorted row), built by its first call after each change of generation.
+    // The bucket scan's planes of the sorted order, built by the first call
+    // that needs one after each change of generation: the first two key words
+    // of every sorted row, and columns of single key words.
     mutable uint64_t* d_splane = nullptr;
     mutable int64_t splane_cap = 0;
     mutable uint64_t splane_gen = ~0ull;
+    mutable std::vector<uint32_t*> d_col;  // [W], null until used
+    mutable uint64_t col_gen = ~0ull;
 
     mutable std::mutex mu;
     mutable std::unordered_map<hipStream_t, StreamCtx*> ctx;
@@ -296,6 +299,31 @@ lcp_status ensure_sorted_plane(const lcp_index* idx, hipStream_t s) {
     return LCP_OK;
 }
 
+// The bucket scan's column of key word w for the current generation (built
+// and waited for on first use, as the pair plane).  Caller holds idx->mu.
+lcp_status ensure_sorted_column(const lcp_index* idx, int w, hipStream_t s) {
+    if (idx->col_gen != idx->generation) {
+        HIP_TRY(hipDeviceSynchronize());  // calls on other streams may still read the old columns
+        for (uint32_t*& c : idx->d_col) {
+            if (c) hipFree(c);
+            c = nullptr;
+        }
+        idx->d_col.assign(idx->g.W, nullptr);
+        idx->col_gen = idx->generation;
+    }
+    if (idx->d_col[w]) return LCP_OK;
+    uint32_t* col = nullptr;
+    HIP_TRY(hipMalloc(&col, (size_t)column_entries(idx->N) * sizeof(uint32_t)));
+    hipError_t e = launch_sorted_column(idx->cp[idx->cur].sorted, idx->N, idx->g.W, w, col, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hipFree(col);
+        return fail(LCP_EDEVICE, "sorted column: %s", hipGetErrorString(e));
+    }
+    idx->d_col[w] = col;
+    return LCP_OK;
+}
+
 lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t Q, const int32_t* k_dev,
                    const int64_t* off_dev, int32_t k_uniform, int32_t k_max, int32_t* out_ids, int32_t* out_lcp,
                    hipStream_t s, StreamCtx* c, int32_t* stats = nullptr, int32_t depth = 0) {
@@ -303,9 +331,12 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
     const IndexView ix = idx->view();
     const size_t row_bytes = (size_t)idx->L * idx->g.tb;
     const int64_t slice = path == Path::Scan ? kSliceScan : kSliceIndex;
+    const void* bucket_plane = nullptr;
     if (path == Path::Bucket) {
-        lcp_status st = ensure_sorted_plane(idx, s);
+        const int cw = bucket_column(depth, idx->g);
+        lcp_status st = cw < 0 ? ensure_sorted_plane(idx, s) : ensure_sorted_column(idx, cw, s);
         if (st != LCP_OK) return st;
+        bucket_plane = cw < 0 ? static_cast<const void*>(idx->d_splane) : static_cast<const void*>(idx->d_col[cw]);
     }
     for (int64_t q0 = 0; q0 < Q; q0 += slice) {
         QueryBatch qb;
@@ -326,7 +357,7 @@ lcp_status run_dev(const lcp_index* idx, Path path, const void* queries, int64_t
         }
         if (path == Path::Bucket) {
             // the bucket bounds travel in `stats` as [Q][2]
-            HIP_TRY(launch_bucket_scan(ix, idx->d_splane, qb, depth, stats ? stats + 2 * q0 : nullptr, s));
+            HIP_TRY(launch_bucket_scan(ix, bucket_plane, qb, depth, stats ? stats + 2 * q0 : nullptr, s));
         } else if (path == Path::Index) {
             if (ev[0]) HIP_TRY(hipEventRecord(ev[0], s));
             HIP_TRY(launch_index_query(ix, qb, s));
@@ -458,6 +489,8 @@ void destroy_index(lcp_index* idx) {
     if (idx->d_rows) hipFree(idx->d_rows);
     if (idx->d_plane) hipFree(idx->d_plane);
     if (idx->d_splane) hipFree(idx->d_splane);
+    for (uint32_t* c : idx->d_col)
+        if (c) hipFree(c);
     idx->cp[0].release();
     idx->cp[1].release();
     idx->app.release();

@@ -6,10 +6,12 @@
 // tokens (a prefix bucket is contiguous in the sorted order) and scans only
 // that range: the LCP of every row in it, and the k best rows by (LCP
 // descending, id ascending).  One wave per query.  The rows are streamed from
-// the sorted prefix plane (the first two key words of each sorted row, 8 bytes
-// a row, coalesced), so a bucket of n rows costs about 8n bytes; the full row
-// is read only where the first two words equal the query's, and the row's id
-// only where the row can still enter the answer.
+// a plane of the sorted order, coalesced: while the prefix ends inside key
+// word 0, the first two key words of each row (8 bytes a row); once it covers
+// whole words, which every row of the bucket shares with the query, only the
+// next word, from a column of that word (4 bytes a row).  The full row is
+// read only where the streamed words equal the query's, and the row's id only
+// where the row can still enter the answer.
 #include "device.hpp"
 #include "launch.hpp"
 
@@ -18,7 +20,8 @@ namespace lcpx {
 namespace {
 
 constexpr int kBucketWaves = 4;     // waves (queries) per block
-constexpr int kBucketUnroll = 2;    // 16-byte plane loads per lane and step
+constexpr int kBucketUnroll = 2;    // 16-byte plane loads per lane and step (pair plane)
+constexpr int kColUnroll = 1;       // the same for a column plane
 constexpr int kBucketMaxW = (255 * 2 + 3) / 4;  // key words of the longest row: 255 two-byte tokens
 
 // Order of the first d tokens of a row against the query's: nw whole key words,
@@ -57,9 +60,19 @@ __device__ __forceinline__ int64_t bucket_bound(const uint32_t* __restrict__ sor
     return a;
 }
 
-template <int NR>
-__global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView ix, const uint64_t* __restrict__ splane,
-                                                                      QueryBatch qb, int depth,
+// Column plane: key word w of every sorted row, zero-padded to a multiple of 4 rows.
+__global__ void k_sorted_column(const uint32_t* __restrict__ sorted, int64_t N, int W, int w,
+                                uint32_t* __restrict__ col) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < column_entries(N)) col[p] = p < N ? sorted[p * W + w] : 0u;
+}
+
+// kCol == false: `plane` is the pair plane (key words 0 and 1 of each sorted
+// row, 8 bytes a row).  kCol == true: `plane` is the column of key word cw,
+// and every row of the bucket shares words 0 .. cw-1 with the query.
+template <int NR, bool kCol>
+__global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView ix, const void* __restrict__ plane,
+                                                                      int cw, QueryBatch qb, int depth,
                                                                       int32_t* __restrict__ bounds) {
     __shared__ uint32_t s_q[kBucketWaves][kBucketMaxW];
     const RowGeo g = ix.g;
@@ -88,66 +101,91 @@ __global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView 
     }
 
     // ---- 2. scan it: LCP of every row, the k best keys kept in a wave list.
-    // Each lane takes two adjacent rows per 16-byte load; a step is
-    // kBucketUnroll loads per lane, and the next step's loads are issued
+    // Each lane takes kRows adjacent rows per 16-byte load; a step is
+    // kU loads per lane, and the next step's loads are issued
     // before this step's rows are compared.  The range is widened to whole
-    // pairs ([lo & ~1, (hi + 1) & ~1) lies inside the plane, whose entry count
-    // is even); rows outside [lo, hi) are masked.
+    // loads ([lo, hi) rounded out to multiples of kRows lies inside the plane,
+    // whose entry count is such a multiple); rows outside [lo, hi) are masked.
+    constexpr int kRows = kCol ? 4 : 2;
     const int k = query_k(qb, qi);
-    const uint64_t qp = ((uint64_t)q[0] << 32) | (g.W > 1 ? q[1] : 0u);
+    const uint64_t qp = kCol ? (uint64_t)q[cw] : ((uint64_t)q[0] << 32) | (g.W > 1 ? q[1] : 0u);
+    const int lcp_base = kCol ? cw << g.tpw_log2 : 0;  // tokens before the streamed words
+    const int tail_from = kCol ? cw + 1 : 2;          // first key word not streamed
     WaveList<NR> list;
     list.init();
     uint64_t thr = kKeyMax;  // the k-th smallest key so far
-    const int64_t a0 = lo & ~(int64_t)1;
-    const int64_t hend = (hi + 1) & ~(int64_t)1;
-    constexpr int kStep = kBucketUnroll * 2 * kWave;
-    auto load_pair = [&](int64_t b, int u) -> uint4 {
-        int64_t p = b + u * 2 * kWave + 2 * lane;
-        p = p < hend ? p : hend - 2;
-        return *reinterpret_cast<const uint4*>(splane + p);
+    const int64_t a0 = lo & ~(int64_t)(kRows - 1);
+    const int64_t hend = (hi + kRows - 1) & ~(int64_t)(kRows - 1);
+    constexpr int kU = kCol ? kColUnroll : kBucketUnroll;
+    constexpr int kStep = kU * kRows * kWave;
+    auto load_rows = [&](int64_t b, int u) -> uint4 {
+        int64_t p = b + (u * kWave + lane) * kRows;
+        p = p < hend ? p : hend - kRows;
+        if constexpr (kCol)
+            return *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(plane) + p);
+        else
+            return *reinterpret_cast<const uint4*>(static_cast<const uint64_t*>(plane) + p);
     };
     auto row_lcp = [&](uint64_t v, int64_t p) -> int {
         const uint64_t x = v ^ qp;
-        int lcp = x ? (int)(__clzll((long long)x) >> g.bits_log2) : g.L;
-        if (x == 0 && g.W > 2 && p < hi) lcp = lcp_tail(ix.sorted + p * g.W, q, g, 2);
+        int lcp;
+        if constexpr (kCol)
+            lcp = x ? lcp_base + (__clz((int)(uint32_t)x) >> g.bits_log2) : g.L;
+        else
+            lcp = x ? (int)(__clzll((long long)x) >> g.bits_log2) : g.L;
+        if (x == 0 && tail_from < g.W && p < hi) lcp = lcp_tail(ix.sorted + p * g.W, q, g, tail_from);
         return lcp;
     };
-    auto scan_step = [&](const uint4 (&buf)[kBucketUnroll], int64_t base) {
+    auto scan_step = [&](const uint4 (&buf)[kU], int64_t base) {
 #pragma unroll
-        for (int u = 0; u < kBucketUnroll; ++u) {
-            const int64_t p0 = base + u * 2 * kWave + 2 * lane;
-            const bool act0 = p0 >= lo && p0 < hi;
-            const bool act1 = p0 + 1 >= lo && p0 + 1 < hi;
-            const int lcp0 = row_lcp(((uint64_t)buf[u].y << 32) | buf[u].x, p0);
-            const int lcp1 = row_lcp(((uint64_t)buf[u].w << 32) | buf[u].z, p0 + 1);
+        for (int u = 0; u < kU; ++u) {
+            const int64_t p0 = base + (u * kWave + lane) * kRows;
+            uint64_t v[kRows];
+            if constexpr (kCol) {
+                v[0] = buf[u].x;
+                v[1] = buf[u].y;
+                v[2] = buf[u].z;
+                v[3] = buf[u].w;
+            } else {
+                v[0] = ((uint64_t)buf[u].y << 32) | buf[u].x;
+                v[1] = ((uint64_t)buf[u].w << 32) | buf[u].z;
+            }
+            int lcp[kRows];
+            bool c[kRows];
+            bool any = false;
             // a row enters only with an LCP of at least the k-th key's (its id decides a tie)
             const int tl = thr == kKeyMax ? -1 : key_lcp(thr);
-            const bool c0 = act0 && lcp0 >= tl;
-            const bool c1 = act1 && lcp1 >= tl;
-            if (ballot(c0 || c1)) {
-                const uint32_t id0 = c0 ? (uint32_t)ix.perm[p0] : 0u;
-                const uint32_t id1 = c1 ? (uint32_t)ix.perm[p0 + 1] : 0u;
-                list.offer(rank_key(lcp0, id0), c0, k);
-                list.offer(rank_key(lcp1, id1), c1, k);
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                lcp[r] = row_lcp(v[r], p0 + r);
+                c[r] = p0 + r >= lo && p0 + r < hi && lcp[r] >= tl;
+                any = any || c[r];
+            }
+            if (ballot(any)) {
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const uint32_t id = c[r] ? (uint32_t)ix.perm[p0 + r] : 0u;
+                    list.offer(rank_key(lcp[r], id), c[r], k);
+                }
                 thr = list.get(k - 1);
             }
         }
     };
     // two register sets in turn: one step's loads are in flight while the
     // other's rows are compared, with no copy between them
-    uint4 ba[kBucketUnroll], bb[kBucketUnroll];
+    uint4 ba[kU], bb[kU];
     if (lo < hi) {
 #pragma unroll
-        for (int u = 0; u < kBucketUnroll; ++u) ba[u] = load_pair(a0, u);
+        for (int u = 0; u < kU; ++u) ba[u] = load_rows(a0, u);
     }
     for (int64_t base = a0; base < hi;) {
 #pragma unroll
-        for (int u = 0; u < kBucketUnroll; ++u) bb[u] = load_pair(base + kStep, u);
+        for (int u = 0; u < kU; ++u) bb[u] = load_rows(base + kStep, u);
         scan_step(ba, base);
         base += kStep;
         if (base >= hi) break;
 #pragma unroll
-        for (int u = 0; u < kBucketUnroll; ++u) ba[u] = load_pair(base + kStep, u);
+        for (int u = 0; u < kU; ++u) ba[u] = load_rows(base + kStep, u);
         scan_step(bb, base);
         base += kStep;
     }
@@ -165,24 +203,44 @@ __global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView 
     }
 }
 
-template <int NR>
-hipError_t launch_bucket_t(const IndexView& ix, const uint64_t* splane, const QueryBatch& qb, int depth,
+template <int NR, bool kCol>
+hipError_t launch_bucket_t(const IndexView& ix, const void* plane, int cw, const QueryBatch& qb, int depth,
                            int32_t* bounds, hipStream_t s) {
     const int64_t blocks = (qb.Q + kBucketWaves - 1) / kBucketWaves;
-    hipLaunchKernelGGL(k_bucket_scan<NR>, dim3((unsigned)blocks), dim3(kBucketWaves * kWave), 0, s, ix, splane, qb,
-                       depth, bounds);
+    hipLaunchKernelGGL((k_bucket_scan<NR, kCol>), dim3((unsigned)blocks), dim3(kBucketWaves * kWave), 0, s, ix, plane,
+                       cw, qb, depth, bounds);
     return hipGetLastError();
+}
+
+template <bool kCol>
+hipError_t launch_bucket_k(const IndexView& ix, const void* plane, int cw, const QueryBatch& qb, int depth,
+                           int32_t* bounds, hipStream_t s) {
+    if (qb.k_max <= 64) return launch_bucket_t<1, kCol>(ix, plane, cw, qb, depth, bounds, s);
+    if (qb.k_max <= 128) return launch_bucket_t<2, kCol>(ix, plane, cw, qb, depth, bounds, s);
+    if (qb.k_max <= 256) return launch_bucket_t<4, kCol>(ix, plane, cw, qb, depth, bounds, s);
+    return launch_bucket_t<16, kCol>(ix, plane, cw, qb, depth, bounds, s);
 }
 
 }  // namespace
 
-hipError_t launch_bucket_scan(const IndexView& ix, const uint64_t* splane, const QueryBatch& qb, int depth,
+int bucket_column(int depth, const RowGeo& g) {
+    if (depth < (1 << g.tpw_log2)) return -1;
+    const int w = depth >> g.tpw_log2;
+    return w < g.W ? w : g.W - 1;
+}
+
+hipError_t launch_sorted_column(const uint32_t* sorted, int64_t N, int W, int w, uint32_t* col, hipStream_t s) {
+    const int64_t n = column_entries(N);
+    hipLaunchKernelGGL(k_sorted_column, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, sorted, N, W, w, col);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_scan(const IndexView& ix, const void* plane, const QueryBatch& qb, int depth,
                               int32_t* bounds, hipStream_t s) {
     if (qb.Q <= 0) return hipSuccess;
-    if (qb.k_max <= 64) return launch_bucket_t<1>(ix, splane, qb, depth, bounds, s);
-    if (qb.k_max <= 128) return launch_bucket_t<2>(ix, splane, qb, depth, bounds, s);
-    if (qb.k_max <= 256) return launch_bucket_t<4>(ix, splane, qb, depth, bounds, s);
-    return launch_bucket_t<16>(ix, splane, qb, depth, bounds, s);
+    const int cw = bucket_column(depth, ix.g);
+    if (cw >= 0) return launch_bucket_k<true>(ix, plane, cw, qb, depth, bounds, s);
+    return launch_bucket_k<false>(ix, plane, 0, qb, depth, bounds, s);
 }
 
 }  // namespace lcpx

@@ -171,10 +171,15 @@ hipError_t launch_scan(const IndexView& ix, const QueryBatch& qb, const ScanPlan
                        hipEvent_t ev_scan0, hipEvent_t ev_scan1, hipEvent_t ev_merge1);
 
 // Prefix-bucket range scan: one wave per query scans the sorted rows sharing
-// its first `depth` tokens.  splane: the first two key words of every sorted
-// row (launch_prefix_plane over the sorted copy).  bounds: null, or [Q][2]
-// int32 receiving each query's bucket [lo, hi) in sorted positions.
-hipError_t launch_bucket_scan(const IndexView& ix, const uint64_t* splane, const QueryBatch& qb, int depth,
+// its first `depth` tokens.  The plane it streams: bucket_column(depth, g) < 0:
+// the first two key words of every sorted row (launch_prefix_plane over the
+// sorted copy); otherwise the column of that key word (launch_sorted_column).
+// bounds: null, or [Q][2] int32 receiving each query's bucket [lo, hi) in
+// sorted positions.
+__host__ __device__ inline int64_t column_entries(int64_t N) { return (N + 3) & ~(int64_t)3; }
+int bucket_column(int depth, const RowGeo& g);
+hipError_t launch_sorted_column(const uint32_t* sorted, int64_t N, int W, int w, uint32_t* col, hipStream_t s);
+hipError_t launch_bucket_scan(const IndexView& ix, const void* plane, const QueryBatch& qb, int depth,
                               int32_t* bounds, hipStream_t s);
 
 }  // namespace lcpx
