@@ -77,6 +77,13 @@ def test_error_paths_without_gpu():
     lib.lcp_topk_stats.restype = ctypes.c_int
     lib.lcp_topk_stats.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64] + [ctypes.c_void_p] * 5
     assert lib.lcp_topk_stats(None, None, 1, None, None, None, None, None) == -1
+    lib.lcp_bucket_scan_topk.restype = ctypes.c_int
+    lib.lcp_bucket_scan_topk.argtypes = ([ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_int32] +
+                                         [ctypes.c_void_p] * 5)
+    assert lib.lcp_bucket_scan_topk(None, None, 1, 2, None, None, None, None, None) == -1
+    assert b"index is NULL" in lib.lcp_last_error()
+    assert lib.lcp_bucket_scan_topk(None, None, 1, 2, None, None, None, 4, None) == -1  # bounds not 8-byte aligned
+    assert b"aligned" in lib.lcp_last_error()
     lib.lcp_index_free(None)
 
 
