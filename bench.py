@@ -71,7 +71,7 @@ def log(args, *a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build targets one GPU: the index and the scan run on a single MI355X; "
+        print(json.dumps({"error": "the index and the scan run on a single MI355X; "
                                    "--gpus must be 1"}))
         sys.exit(2)
 

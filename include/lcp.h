@@ -52,7 +52,7 @@ typedef enum {
     LCP_ENOMEM = -2,   /* a device or pinned-host allocation failed */
     LCP_EDEVICE = -3,  /* a HIP runtime call failed */
     LCP_ERANGE = -4,   /* lcp_index_build found a token >= V */
-    LCP_ENOTIMPL = -5  /* the request is valid but not supported by this build */
+    LCP_ENOTIMPL = -5  /* the request is valid but not supported by this library */
 } lcp_status;
 
 #define LCP_L_MAX 255   /* LCP values are stored in one byte */
