@@ -38,26 +38,34 @@ __device__ __forceinline__ int cmp_prefix(const uint32_t* __restrict__ row, cons
     return 0;
 }
 
-// First sorted position p in [a, b) whose row's d-prefix is >= the query's
-// (upper == false) or > it (upper == true); b when there is none.  64-ary:
-// each step probes the last position of 64 equal segments, one per lane, and
-// keeps the segment where the predicate turns.
-__device__ __forceinline__ int64_t bucket_bound(const uint32_t* __restrict__ sorted, int W, const uint32_t* q, int nw,
-                                                uint32_t mask, int64_t a, int64_t b, bool upper) {
+// Both ends of the bucket at once: lanes 0-31 find the first sorted position
+// whose row's d-prefix is >= the query's (lo), lanes 32-63 the first whose
+// prefix is > it (hi).  Each half runs a 32-ary search over [0, N): per step
+// its lanes probe the last position of 32 equal segments of the half's range
+// and keep the segment where its predicate turns.
+__device__ __forceinline__ void bucket_bounds(const uint32_t* __restrict__ sorted, int W, const uint32_t* q, int nw,
+                                              uint32_t mask, int64_t N, int64_t& lo, int64_t& hi) {
+    constexpr int kHalf = kWave / 2;
     const int lane = lane_id();
-    while (a < b) {
-        const int64_t s = (b - a + kWave - 1) / kWave;
-        const int64_t p = a + (int64_t)(lane + 1) * s - 1;
-        const bool valid = p < b;
+    const bool upper = lane >= kHalf;
+    const int j = lane & (kHalf - 1);
+    int64_t a = 0, b = N;  // the half's range: its answer lies in [a, b]
+    while (ballot(a < b)) {
+        const int64_t s = (b - a + kHalf - 1) / kHalf;
+        const int64_t p = a + (int64_t)(j + 1) * s - 1;
+        const bool valid = a < b && p < b;
         const int c = valid ? cmp_prefix(sorted + p * W, q, nw, mask) : 1;
         const bool before = valid && (upper ? c <= 0 : c < 0);
-        const int64_t cnt = popc64(ballot(before));
-        const int64_t na = a + cnt * s;
-        const int64_t nb = a + (cnt + 1) * s - 1;
-        a = na;
-        b = nb < b ? nb : b;
+        const uint64_t bal = ballot(before);
+        const int64_t cnt = popc64(upper ? bal >> kHalf : bal & ((1ull << kHalf) - 1));
+        if (a < b) {
+            const int64_t nb = a + (cnt + 1) * s - 1;
+            a += cnt * s;
+            b = nb < b ? nb : b;
+        }
     }
-    return a;
+    lo = readlane_i64(a, 0);
+    hi = readlane_i64(a, kHalf);
 }
 
 // Column plane: key word w of every sorted row, zero-padded to a multiple of 4 rows.
@@ -92,8 +100,7 @@ __global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView 
         const int nw = depth >> g.tpw_log2;
         const int rem = depth & ((1 << g.tpw_log2) - 1);
         const uint32_t mask = rem ? ~0u << (32 - (rem << g.bits_log2)) : 0u;
-        lo = bucket_bound(ix.sorted, g.W, q, nw, mask, 0, ix.N, false);
-        hi = bucket_bound(ix.sorted, g.W, q, nw, mask, lo, ix.N, true);
+        bucket_bounds(ix.sorted, g.W, q, nw, mask, ix.N, lo, hi);
     }
     if (bounds && lane == 0) {
         bounds[2 * qi] = (int32_t)lo;
