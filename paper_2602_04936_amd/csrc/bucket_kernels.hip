@@ -20,8 +20,10 @@ namespace lcpx {
 namespace {
 
 constexpr int kBucketWaves = 4;     // waves (queries) per block
-constexpr int kBucketUnroll = 2;    // 16-byte plane loads per lane and step (pair plane)
+constexpr int kBucketUnroll = 1;    // 16-byte plane loads per lane and step (pair plane)
 constexpr int kColUnroll = 1;       // the same for a column plane
+// k <= 64 (one list register): at most 64 VGPRs, so that 8 waves fit per SIMD
+// and a whole 8,192-query batch is resident at once
 constexpr int kBucketMaxW = (255 * 2 + 3) / 4;  // key words of the longest row: 255 two-byte tokens
 
 // Order of the first d tokens of a row against the query's: nw whole key words,
@@ -79,7 +81,7 @@ __global__ void k_sorted_column(const uint32_t* __restrict__ sorted, int64_t N, 
 // row, 8 bytes a row).  kCol == true: `plane` is the column of key word cw,
 // and every row of the bucket shares words 0 .. cw-1 with the query.
 template <int NR, bool kCol>
-__global__ __launch_bounds__(kBucketWaves * kWave) void k_bucket_scan(IndexView ix, const void* __restrict__ plane,
+__global__ __launch_bounds__(kBucketWaves * kWave) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 8 : 1))) void k_bucket_scan(IndexView ix, const void* __restrict__ plane,
                                                                       int cw, QueryBatch qb, int depth,
                                                                       int32_t* __restrict__ bounds) {
     __shared__ uint32_t s_q[kBucketWaves][kBucketMaxW];
