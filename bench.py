@@ -749,9 +749,13 @@ def prefix_bucket_sweep(P, idx, q_dev, k, meter=None, seconds=0.0, idle=None):
         e1.record()
         torch.cuda.synchronize()
         gpu_ms = e0.elapsed_time(e1) / reps
+        # bytes a row the scan streams: key words 0-1 (8) until the prefix covers a whole word, then one word (4)
+        per_row = 8 if d * idx.token_bytes < 4 else 4
+        streamed = float(rows.sum()) * per_row
         rec = {"depth": d, "buckets_with_queries": buckets, "queries": Q,
                "mean_rows_scanned": round(float(rows.mean()), 1), "empty_bucket_queries": int((rows == 0).sum()),
-               "gpu_ms_per_batch": round(gpu_ms, 4), "gpu_qps": round(Q / (gpu_ms * 1e-3), 1)}
+               "gpu_ms_per_batch": round(gpu_ms, 4), "gpu_qps": round(Q / (gpu_ms * 1e-3), 1),
+               "plane_bytes_per_row": per_row, "streamed_GBps": round(streamed / (gpu_ms * 1e-3) / 1e9, 1)}
         if meter is not None:
             def run():
                 idx.bucket_scan_topk(q_dev, k, d, out=o)
