@@ -22,8 +22,6 @@ namespace {
 constexpr int kBucketWaves = 4;     // waves (queries) per block
 constexpr int kBucketUnroll = 1;    // 16-byte plane loads per lane and step (pair plane)
 constexpr int kColUnroll = 1;       // the same for a column plane
-// k <= 64 (one list register): at most 64 VGPRs, so that 8 waves fit per SIMD
-// and a whole 8,192-query batch is resident at once
 constexpr int kBucketMaxW = (255 * 2 + 3) / 4;  // key words of the longest row: 255 two-byte tokens
 
 // Order of the first d tokens of a row against the query's: nw whole key words,
@@ -80,10 +78,12 @@ __global__ void k_sorted_column(const uint32_t* __restrict__ sorted, int64_t N, 
 // kCol == false: `plane` is the pair plane (key words 0 and 1 of each sorted
 // row, 8 bytes a row).  kCol == true: `plane` is the column of key word cw,
 // and every row of the bucket shares words 0 .. cw-1 with the query.
+// With one list register (k <= 64) the kernel is held to 64 VGPRs, so that 8
+// waves fit per SIMD and a whole 8,192-query batch is resident at once.
 template <int NR, bool kCol>
-__global__ __launch_bounds__(kBucketWaves * kWave) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 8 : 1))) void k_bucket_scan(IndexView ix, const void* __restrict__ plane,
-                                                                      int cw, QueryBatch qb, int depth,
-                                                                      int32_t* __restrict__ bounds) {
+__global__ __launch_bounds__(kBucketWaves * kWave) __attribute__((amdgpu_waves_per_eu(NR == 1 ? 8 : 1))) void
+k_bucket_scan(IndexView ix, const void* __restrict__ plane, int cw, QueryBatch qb, int depth,
+              int32_t* __restrict__ bounds) {
     __shared__ uint32_t s_q[kBucketWaves][kBucketMaxW];
     const RowGeo g = ix.g;
     const int lane = lane_id();
