@@ -170,3 +170,41 @@ def test_c3_full_size_sampled_and_against_the_index_path(P):
                 assert int(size[i]) == m, (d, int(i))
                 assert (gi[i, :m] == fi[i, :m]).all() and (gl[i, :m] == fl[i, :m]).all(), (d, int(i))
                 assert (gi[i, m:] == -1).all() and (gl[i, m:] == -1).all(), (d, int(i))
+
+
+def test_query_tokens_beyond_the_vocabulary(P):
+    """Query tokens >= V compare as integers (their bucket is empty, or shorter
+    than d when the token comes later)."""
+    rng = np.random.default_rng(23)
+    for V, L in ((16, 10), (300, 6)):
+        db = synth.random_rows(rng, 3000, L, V)
+        qs = db[rng.integers(0, 3000, 24)].copy()
+        big = np.iinfo(qs.dtype).max
+        qs[::3, 0] = big          # empty bucket at every depth >= 1
+        qs[1::3, L // 2] = big    # the bucket is the rows' own up to L/2
+        _check(P, db, qs, rng.integers(1, 40, qs.shape[0]).astype(np.int32), V, [0, 1, L // 2, L // 2 + 1, L],
+               f"tokens >= V, V={V}")
+
+
+def test_two_streams_share_the_sorted_planes(P):
+    """Calls on two streams after an append: the first call that needs a plane
+    lays it out and waits, later calls on either stream read it."""
+    import torch
+    rng = np.random.default_rng(31)
+    L, V = 12, 8
+    a = synth.random_rows(rng, 4000, L, V)
+    b = synth.random_rows(rng, 500, L, V)
+    qs = np.concatenate([a[rng.integers(0, 4000, 30)], synth.random_rows(rng, 10, L, V)])
+    ks = rng.integers(1, 50, qs.shape[0]).astype(np.int32)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    with P.Index(a, V) as idx:
+        idx.append(b)
+        db = np.concatenate([a, b])
+        q = P.to_device_tokens(qs, torch.device("cuda:0"))
+        outs = []
+        for i, d in enumerate((0, 5, 2, 9, 0, 5)):
+            outs.append((d, idx.bucket_scan_topk(q, ks, d, stream=streams[i % 2])))
+        torch.cuda.synchronize()
+        for d, r in outs:
+            wi, wl, _ = O.bucket_topk_batch(db, qs, ks, d)
+            _assert_equal(r.ids.cpu().numpy(), r.lcps.cpu().numpy(), wi, wl, r.offsets, f"two streams depth {d}")
